@@ -1,0 +1,196 @@
+/*
+ * sigw.h -- C ABI of the MI355X (gfx950) library that computes the
+ * scalar-induced gravitational-wave spectrum Omega^(RD)_GW(k) of a (non-)
+ * Gaussian curvature field on a 3D periodic lattice, by the separable-kernel
+ * convolution method of arXiv 2605.27231 (Piccoli).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: N sites per side (even), box side L, k_F = 2 pi / L, cell volume
+ *   dV = (L/N)^3, volume V = L^3.  Modes n are integer triples with signed
+ *   representatives in [-N/2, N/2); q = k_F n.
+ * Fourier convention (Sec. III two-point function, Sec. IV real-space fields):
+ *   X_hat(n) = dV sum_x exp(-i q.x) X(x),  X(x) = (1/V) sum_n exp(i q.x) X_hat(n).
+ * Layouts (row-major, last index fastest, no padding):
+ *   real field      [x][y][z], N*N*N elements of the path precision;
+ *   half spectrum   [kx][ky][kz] with kx = 0..N/2 (the first axis is halved;
+ *                   kx = N/2 is the Nyquist plane), ky, kz = 0..N-1;
+ *                   (N/2+1)*N*N complex elements, interleaved (re, im) of the
+ *                   path precision.  It equals numpy.fft.fftn(X)[:N//2+1] * dV.
+ * Precision: SIGW_F32 runs fields and FFTs in float/complex64, SIGW_F64 in
+ *   double/complex128.  Shell sums, the <zeta_g^2> reduction, the maps and all
+ *   lookup tables are FP64 in both.
+ * Streams: a plan enqueues all device work on the HIP stream given at
+ *   creation (NULL = the null stream).  Entry points that return host results
+ *   synchronise that stream; the others only enqueue.
+ * Memory: device pointers are borrowed for the duration of the call (the work
+ *   they feed is enqueued on the plan stream, so the caller keeps them alive
+ *   until that stream reaches the call); host pointers are read or written
+ *   before the call returns.  The plan owns every buffer it allocates and
+ *   frees them in sigw_plan_destroy.
+ * Errors: no exception crosses the ABI.  Invalid arguments return
+ *   SIGW_E_INVALID and change nothing; a HIP failure returns SIGW_E_DEVICE;
+ *   a call out of order (e.g. a spectrum before any field) returns
+ *   SIGW_E_STATE.  sigw_last_error(plan) gives a text for the last failure.
+ * Threads: a plan is used by one host thread at a time; distinct plans are
+ *   independent and may run concurrently on different streams.
+ */
+#ifndef SIGW_H
+#define SIGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sigw_plan* sigw_plan_t;
+
+typedef enum {
+    SIGW_OK = 0,
+    SIGW_E_INVALID = -1,
+    SIGW_E_NOMEM = -2,
+    SIGW_E_DEVICE = -3,
+    SIGW_E_UNSUPPORTED = -4,
+    SIGW_E_STATE = -5,
+    SIGW_E_PENDING = -6
+} sigw_status;
+
+typedef enum { SIGW_F32 = 0, SIGW_F64 = 1 } sigw_prec;
+
+typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2 } sigw_map_kind;
+
+/* Plan description: the lattice and the separable decomposition of Sec. V.
+ * N must be one of 8, 16, 32, 64, 128, 256, 384, 512 (2^a 3^b sizes with a
+ * compiled FFT schedule).  n_modes intervals on [u_min, u_max) with the grid
+ * density rho(u) = 1 + A_p exp(-(u-u_p)^2 / (2 sigma_p^2)) (Eq. grid_density);
+ * 1 <= n_alpha <= n_modes terms are kept (Eq. decomposition).
+ * n_slots is the number of device-resident Phi_hat fields (realisations) the
+ * plan holds, >= 1.  alpha_chunk bounds how many separable terms share one
+ * workspace pass (0 = all n_alpha; a smaller value trades a few extra
+ * read-modify-write passes for 3*alpha_chunk instead of 3*n_alpha fields of
+ * workspace). */
+typedef struct {
+    int32_t N;
+    double  L;
+    int32_t prec;        /* sigw_prec */
+    int32_t n_slots;
+    int32_t n_modes;
+    int32_t n_alpha;
+    double  u_min, u_max, u_p, sigma_p, A_p;
+    int32_t alpha_chunk;
+} sigw_plan_desc;
+
+/* Log-normal peak, Eq. lognormal: Delta^2(k) = A/sqrt(2 pi sigma^2) exp(-ln^2(k/k_star)/(2 sigma^2)).
+ * The field's spectrum is P(k) = 2 pi^2 Delta^2(k) / k^3.  A >= 0, sigma > 0, k_star > 0. */
+typedef struct { double A, sigma, k_star; } sigw_lognormal;
+
+/* Non-Gaussian map (Sec. VI B and the exponential-tail family):
+ *   GAUSS:   zeta = zeta_g
+ *   LOCAL:   zeta = zeta_g + F_NL (zeta_g^2 - <zeta_g^2>) + G_NL zeta_g^3,
+ *            <zeta_g^2> the FP64 mean over the lattice
+ *   EXPTAIL: zeta = -ln(max(1 - beta zeta_g, clip)) / beta, beta > 0, clip > 0 */
+typedef struct { int32_t kind; double F_NL, G_NL, beta, clip; } sigw_ngmap;
+
+/* Fill d with the paper's default decomposition (n_modes 200, n_alpha 50,
+ * u in [1e-3, 15), u_p 1, sigma_p 0.5, A_p 10), one slot, all terms per pass. */
+sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32_t prec);
+
+/* Device bytes a plan with this description allocates (for admission by HBM
+ * budget).  Host only; no device is touched. */
+sigw_status sigw_plan_footprint(const sigw_plan_desc* d, size_t* bytes);
+
+/* Build a plan: validate, build the kernel tables on the host (Sec. V:
+ * u-grid, C_ij = sqrt(L_i L_j) I(c_i, c_j) on the triangle strip, symmetric
+ * eigen-decomposition, keep n_alpha terms by |sigma|), upload them, build the
+ * FFT twiddles and allocate the workspace.  hip_stream is a hipStream_t or
+ * NULL.  On success *out owns everything it allocated. */
+sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_plan_t* out);
+sigw_status sigw_plan_destroy(sigw_plan_t plan);
+
+/* Host-only copy of the kernel table the plan would use for kernel m
+ * (0 = I_s, 1 = I_c, Eq. kernels): sigma[n_alpha] (ordered by |sigma|
+ * descending), phi[n_modes * n_alpha] (phi_a on interval i at
+ * phi[i * n_alpha + a]), edges[n_modes + 1].  Any output may be NULL. */
+sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma, double* phi,
+                              double* edges);
+
+/* White noise of one seed: one N(0,1) deviate per site (Philox4x64-10 with
+ * key (seed, 0) and counter (site, 0, 0, 0), site = (x N + y) N + z; the
+ * Box-Muller cosine branch with the binary64 ln/cos sequence documented in
+ * the implementation), rounded to the path precision, written as a real field
+ * to out_dev (N^3 elements).  Enqueues only. */
+sigw_status sigw_white_noise(sigw_plan_t plan, uint64_t seed, void* out_dev);
+
+/* Generate the realisation of one seed into a slot (Sec. VI): white noise,
+ * zeta_g_hat = sqrt(dV P(k_F|n|)) DFT(noise) with the k = 0 mode removed,
+ * zeta_g, the map, Phi = 2 zeta / 3 (Sec. II at w = 1/3) and
+ * Phi_hat = dV DFT(Phi), which stays on the device.  Enqueues only. */
+sigw_status sigw_generate_field(sigw_plan_t plan, int32_t slot, uint64_t seed,
+                                const sigw_lognormal* spectrum, const sigw_ngmap* ngmap);
+
+/* Use a caller's own real curvature field zeta (device, real layout, path
+ * precision) for a slot: Phi_hat = dV DFT(2 zeta / 3).  Enqueues only. */
+sigw_status sigw_set_zeta(sigw_plan_t plan, int32_t slot, const void* zeta_dev);
+
+/* Copy a half spectrum Phi_hat into / out of a slot (device, half layout). */
+sigw_status sigw_set_phi_hat(sigw_plan_t plan, int32_t slot, const void* phi_hat_dev);
+sigw_status sigw_get_phi_hat(sigw_plan_t plan, int32_t slot, void* phi_hat_dev);
+
+/* The source convolutions of one target (Eq. final_envelopes), unfused
+ * output for inspection: for kernels m = 0 (s), 1 (c) and components
+ * c = xx, yy, zz, xy, xz, yz, writes
+ *   Q_hat^(m)_c = dV DFT( sum_a sigma_a G_a,i G_a,j ),
+ *   G_a,j = (1/V) sum_n exp(i q.x) i qt_j phi_a(k_F |n| / k_target) Phi_hat(n)
+ * to qhat_dev as 12 consecutive half spectra [m][c][kx][ky][kz].
+ * qt_j = k_F n_j, zero where n_j = -N/2.  Enqueues only. */
+sigw_status sigw_source_convolutions(sigw_plan_t plan, int32_t slot, double k_target,
+                                     void* qhat_dev);
+
+/* Omega^(RD)_GW at n_k targets (Sec. III, IV).  Target b uses the
+ * convolutions at k_targets[b] and the shell of modes n != 0 with
+ * k_lo[b] <= k_F |n| < k_hi[b]:
+ *   S_b = sum_{n in shell} sum_{m} sum_lambda |e^lambda : X^(m)(n)|^2,
+ *   X^(s) = -(4/k_b^2) Q_hat^(s),  X^(c) = +(4/k_b^2) Q_hat^(c),
+ *   Omega_b = k_b^3 S_b / (48 pi^2 V N_b),  N_b = number of modes in the shell.
+ * Shells with no mode give Omega_b = 0, N_b = 0 and cost nothing.
+ * Writes omega_host[n_k] and nmodes_host[n_k] (either may be NULL) and
+ * synchronises the plan stream. */
+sigw_status sigw_spectrum(sigw_plan_t plan, int32_t slot, int32_t n_k, const double* k_targets,
+                          const double* k_lo, const double* k_hi, double* omega_host,
+                          int64_t* nmodes_host);
+
+/* The same for several slots that share the targets: omega_host[s * n_k + b]
+ * for s = 0..n_sel-1 over slots[s].  Synchronises. */
+sigw_status sigw_spectrum_batch(sigw_plan_t plan, int32_t n_sel, const int32_t* slots,
+                                int32_t n_k, const double* k_targets, const double* k_lo,
+                                const double* k_hi, double* omega_host, int64_t* nmodes_host);
+
+/* Asynchronous form for serving loops: enqueue the spectrum of one slot
+ * (n_k <= 64) and return at once; sigw_spectrum_poll returns SIGW_E_PENDING
+ * until the plan stream has finished that work, then writes the results as
+ * sigw_spectrum does.  Only one asynchronous spectrum per plan is in flight. */
+sigw_status sigw_spectrum_enqueue(sigw_plan_t plan, int32_t slot, int32_t n_k,
+                                  const double* k_targets, const double* k_lo, const double* k_hi);
+sigw_status sigw_spectrum_poll(sigw_plan_t plan, double* omega_host, int64_t* nmodes_host);
+
+/* Block until the plan stream is idle. */
+sigw_status sigw_synchronize(sigw_plan_t plan);
+
+/* Kernel timing of the last completed sigw_spectrum / sigw_spectrum_batch /
+ * sigw_spectrum_enqueue: average duration in milliseconds of the launches of
+ * the named kernel ("gen_z", "ypass", "xprod", "zbin"), measured with HIP
+ * events on the plan stream when timing is enabled, and the number of
+ * launches.  Timing is off by default. */
+sigw_status sigw_set_timing(sigw_plan_t plan, int32_t enabled);
+sigw_status sigw_kernel_time(sigw_plan_t plan, const char* name, double* avg_ms, int64_t* launches);
+
+const char* sigw_last_error(sigw_plan_t plan);
+const char* sigw_status_string(sigw_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIGW_H */

@@ -20,7 +20,17 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = os.cpu_count() or 1
+def _threads() -> int:
+    """Host threads for the FFT library: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+_WORKERS = _threads()
 _AXES = (1, 2, 0)   # transform order; the last axis listed (x) is the halved one
 
 

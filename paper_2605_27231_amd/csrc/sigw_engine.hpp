@@ -1,0 +1,75 @@
+// Interface between the host-side plan (sigw_plan.cpp) and the templated
+// device kernels (sigw_kernels.hip).  One Engine instance exists per plan,
+// specialised for the plan's precision and lattice size; each method enqueues
+// exactly one kernel launch (so that it can be timed on its own) unless noted.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sigw {
+
+struct MapParams {
+    int kind;          // 0 Gaussian, 1 local, 2 exponential tail
+    double F_NL, G_NL, beta, clip;
+};
+
+struct Engine {
+    virtual ~Engine() = default;
+    virtual int N() const = 0;
+    virtual size_t real_bytes() const = 0;      // sizeof of the path real type
+    virtual size_t complex_bytes() const = 0;   // sizeof of the path complex type
+    virtual int zbin_blocks() const = 0;         // partial sums produced by zbin
+    virtual int sumsq_blocks() const = 0;
+
+    // Philox white noise, one deviate per site (real layout).
+    virtual void noise(uint64_t seed, void* real_out, hipStream_t s) = 0;
+    // Forward DFT along x of a real field into the half layout.
+    virtual void xpass_r2c(const void* real_in, void* half_out, hipStream_t s) = 0;
+    // Inverse DFT along x of a half spectrum into a real field.
+    virtual void xpass_c2r(const void* half_in, void* real_out, hipStream_t s) = 0;
+    // Complex DFT along y, in place, of n_fields half spectra spaced by
+    // field_stride complex elements, on the kx planes [0, n_planes).
+    virtual void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign,
+                       hipStream_t s) = 0;
+    // Complex DFT along z, in place, of n_rows contiguous rows.
+    virtual void zpass(void* data, long n_rows, int sign, hipStream_t s) = 0;
+    // Multiply a half spectrum by amp[|n|^2] (FP64 table, rounded to the path precision).
+    virtual void filter(void* half, const double* amp_by_n2, hipStream_t s) = 0;
+    // out[0] = sum_x X(x)^2 in FP64 (two launches: block partials, fixed-order total).
+    virtual void sumsq(const void* real, double* partials, double* out, hipStream_t s) = 0;
+    // real_out = scale * map(real_in), evaluated in FP64; m2 = <zeta_g^2> on the device.
+    virtual void map_scale(const void* real_in, void* real_out, const double* sum_sq,
+                           const MapParams& mp, double scale, hipStream_t s) = 0;
+    // Per-target tables over integer |n|^2 in [0, 3 (N/2)^2]: u-interval index
+    // of u = k_F sqrt(n2) / k_target (-1 outside) and shell membership
+    // k_lo <= k_F sqrt(n2) < k_hi, n2 > 0.
+    virtual void lut(double k_F, double k_target, double k_lo, double k_hi, const double* edges,
+                     int n_modes, int16_t* lut_u, uint8_t* lut_shell, hipStream_t s) = 0;
+    // Fused weighting + inverse DFT along z: for a = a0..a0+na-1 and j = x, y, z,
+    // T[3(a-a0)+j] = IDFT_z( i qt_j phi_a(u) Phi_hat / V ).
+    virtual void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab,
+                       int n_alpha, int a0, int na, double k_F, double inv_V, void* T,
+                       hipStream_t s) = 0;
+    // Fused inverse DFT along x + products + forward DFT along x:
+    // Qx_c = DFT_x( sum_a sigma_a dV G_a,i G_a,j ) for the 6 components, on
+    // the kx planes [0, n_planes); accumulate adds into Qx instead of storing.
+    virtual void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV,
+                       void* Qx, int n_planes, int accumulate, hipStream_t s) = 0;
+    // Fused forward DFT along z of the 12 components (both kernels) + TT
+    // projection + shell sums: one (sum, count) partial per block.
+    virtual void zbin(const void* Qxy, const uint8_t* lut_shell, int n2_lo, int n2_hi,
+                      double* partial_sum, unsigned long long* partial_cnt, hipStream_t s) = 0;
+    // Fixed-order reduction of n partials into out_sum[0], out_cnt[0].
+    virtual void finalize(const double* partial_sum, const unsigned long long* partial_cnt, int n,
+                          double* out_sum, unsigned long long* out_cnt, hipStream_t s) = 0;
+};
+
+// Returns nullptr for an unsupported (prec, N).
+Engine* make_engine(int prec, int N, const void* twiddles_dev);
+// Host twiddles exp(-2 pi i t / N), t = 0..N-1, in the path precision (interleaved).
+void host_twiddles(int prec, int N, void* out);
+
+}  // namespace sigw

@@ -1,0 +1,861 @@
+// HIP kernels of the Omega_GW lattice path for gfx950 (CDNA4, wave64).
+//
+// Data layouts (row-major, last index fastest):
+//   real field    [x][y][z]                   N^3 reals
+//   half spectrum [kx][ky][kz], kx = 0..N/2   (N/2+1) N^2 complex
+// A 3D inverse transform runs z (complex, contiguous rows), then y (complex,
+// strided), then x (the halved axis, complex-to-real); the forward transform
+// runs the same passes in reverse order.  Every pass stages a tile through
+// LDS so that global accesses are runs of at least 64-128 contiguous bytes.
+//
+// The hot loop for one target k fuses the Fourier weighting into the first
+// inverse pass (gen_z), the products and the first forward pass into the last
+// inverse pass (xprod), and the TT projection and FP64 shell sums into the
+// last forward pass (zbin).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sigw_engine.hpp"
+#include "sigw_fft.hpp"
+
+namespace sigw {
+
+// ----------------------------------------------------------------------------
+// Tile shapes per (precision, N)
+// ----------------------------------------------------------------------------
+template <typename R, int N> struct Shape {
+    static constexpr int H = N / 2 + 1;
+    static constexpr long FS = long(H) * N * N;           // complex elements per half spectrum
+    // y-pass / x-pass chunk of contiguous z values (128-byte runs of complex)
+    static constexpr int TZ = (sizeof(R) == 4 ? 16 : 8) < N ? (sizeof(R) == 4 ? 16 : 8) : N;
+    // xprod chunk: keeps the LDS tile near 50 KB
+    static constexpr int TZX0 = (N >= 384) ? (sizeof(R) == 4 ? 8 : 4) : (sizeof(R) == 4 ? 16 : 8);
+    static constexpr int TZX = TZX0 < N ? TZX0 : N;
+    static constexpr int PX = TZX / 2;                    // z pairs per xprod tile
+    // threads per xprod block: a divisor of the N * PX point pairs, at most 512
+    static constexpr int NPP = N * PX;
+    static constexpr int NTX = NPP <= 512 ? NPP : (NPP % 512 == 0 ? 512 : (NPP % 384 == 0 ? 384 : 256));
+    static constexpr int PPX = NPP / NTX;                 // point pairs per thread
+    static_assert(NTX * PPX == NPP, "xprod threads must tile the point pairs");
+    // z-pass rows per block
+    static constexpr int RBZ = (N >= 1024) ? 1 : (N >= 512 ? 4 : (N >= 256 ? 8 : (2048 / N)));
+    static constexpr int RBZ_ = (N == 384) ? 4 : RBZ;
+    // gen_z rows per block (a divisor of N, so blocks tile the (N/2+1) N rows)
+    static constexpr int RBG = (N >= 512) ? 1 : (512 / N < N ? 512 / N : N);
+    static constexpr int RBG_ = (N == 384) ? 1 : RBG;
+    // zbin rows per block (a divisor of N)
+    static constexpr int RBB = (N >= 256) ? 1 : (256 / N < N ? 256 / N : N);
+    static constexpr int RBB_ = (N == 384) ? 1 : RBB;
+    static constexpr int N2MAX = 3 * (N / 2) * (N / 2);
+};
+
+__device__ __forceinline__ int signed_index(int i, int N) { return i < N / 2 ? i : i - N; }
+
+// ----------------------------------------------------------------------------
+// White noise: Philox4x64-10 (Salmon et al., SC'11) + Box-Muller cosine branch.
+// The binary64 ln and cos below follow an explicit operation sequence with no
+// contraction, so that the deviates are reproducible bit for bit by any
+// implementation of the same sequence.
+// ----------------------------------------------------------------------------
+struct Philox4x64 {
+    static constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull;
+    static constexpr uint64_t M1 = 0xCA5A826395121157ull;
+    static constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull;
+    static constexpr uint64_t W1 = 0xBB67AE8584CAA73Bull;
+};
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += Philox4x64::W0;
+            k1 += Philox4x64::W1;
+        }
+        const uint64_t hi0 = __umul64hi(Philox4x64::M0, c[0]);
+        const uint64_t lo0 = Philox4x64::M0 * c[0];
+        const uint64_t hi1 = __umul64hi(Philox4x64::M1, c[2]);
+        const uint64_t lo1 = Philox4x64::M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+#pragma clang fp contract(off)
+__device__ __noinline__ double spec_ln(double u) {
+    constexpr double LN2 = 0.6931471805599453;
+    constexpr double SQRT2 = 1.4142135623730951;
+    constexpr double C[13] = {1.0 / 1.0,  1.0 / 3.0,  1.0 / 5.0,  1.0 / 7.0,  1.0 / 9.0,
+                              1.0 / 11.0, 1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0,
+                              1.0 / 21.0, 1.0 / 23.0, 1.0 / 25.0};
+    int e0;
+    const double m0 = frexp(u, &e0);
+    double m = m0 * 2.0;
+    double e = (double)(e0 - 1);
+    if (m > SQRT2) {
+        m = m * 0.5;
+        e = e + 1.0;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = C[12];
+    for (int k = 11; k >= 0; --k) {
+        p = p * z;
+        p = p + C[k];
+    }
+    const double t = s + s;
+    const double a = e * LN2;
+    const double b = t * p;
+    return a + b;
+}
+
+__device__ __noinline__ double spec_cos2pi(double u) {
+    constexpr double PIO2 = 1.5707963267948966;
+    constexpr double CC[10] = {1.0,
+                               -1.0 / 2.0,
+                               1.0 / 24.0,
+                               -1.0 / 720.0,
+                               1.0 / 40320.0,
+                               -1.0 / 3628800.0,
+                               1.0 / 479001600.0,
+                               -1.0 / 87178291200.0,
+                               1.0 / 20922789888000.0,
+                               -1.0 / 6402373705728000.0};
+    constexpr double SC[10] = {1.0,
+                               -1.0 / 6.0,
+                               1.0 / 120.0,
+                               -1.0 / 5040.0,
+                               1.0 / 362880.0,
+                               -1.0 / 39916800.0,
+                               1.0 / 6227020800.0,
+                               -1.0 / 1307674368000.0,
+                               1.0 / 355687428096000.0,
+                               -1.0 / 121645100408832000.0};
+    const double t = u * 4.0;
+    const double q = floor(t);
+    const double f = t - q;
+    const bool hi = f > 0.5;
+    const double g = hi ? 1.0 - f : f;
+    const double x = g * PIO2;
+    const double z = x * x;
+    double c = CC[9];
+    for (int k = 8; k >= 0; --k) {
+        c = c * z;
+        c = c + CC[k];
+    }
+    double sp = SC[9];
+    for (int k = 8; k >= 0; --k) {
+        sp = sp * z;
+        sp = sp + SC[k];
+    }
+    const double sn = x * sp;
+    const double cf = hi ? sn : c;
+    const double sf = hi ? c : sn;
+    const int qi = (int)q;
+    return qi == 0 ? cf : (qi == 1 ? -sf : (qi == 2 ? -cf : sf));
+}
+
+__device__ __noinline__ double spec_normal(uint64_t w0, uint64_t w1) {
+    const double u1 = ((double)(w0 >> 12) * 2.0 + 1.0) * 0x1.0p-53;
+    const double u2 = ((double)(w1 >> 12) * 2.0 + 1.0) * 0x1.0p-53;
+    const double l = spec_ln(u1);
+    const double r = sqrt(l * -2.0);
+    return r * spec_cos2pi(u2);
+}
+#pragma clang fp contract(fast)
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_noise(R* __restrict__ out, long total, uint64_t seed) {
+    const long s = long(blockIdx.x) * 256 + threadIdx.x;
+    if (s >= total) return;
+    uint64_t c[4] = {(uint64_t)s, 0ull, 0ull, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    out[s] = (R)spec_normal(c[0], c[1]);
+}
+
+// ----------------------------------------------------------------------------
+// z pass: complex DFT along contiguous rows, in place.
+// ----------------------------------------------------------------------------
+template <typename R, int N, int SIGN>
+__global__ __launch_bounds__(256) void k_zpass(typename CplxOf<R>::T* __restrict__ data, long n_rows,
+                                               const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int RB = Shape<R, N>::RBZ_;
+    constexpr int NT = 256;
+    __shared__ C buf[RB * N];
+    const int tid = threadIdx.x;
+    const long row0 = long(blockIdx.x) * RB;
+    for (int e = tid; e < RB * N; e += NT) {
+        const long r = row0 + e / N;
+        buf[e] = (r < n_rows) ? data[r * N + (e % N)] : cmk<C>(R(0), R(0));
+    }
+    __syncthreads();
+    lds_fft<C, N, RB, NT, SIGN, N, 1>(buf, tw, tid);
+    for (int e = tid; e < RB * N; e += NT) {
+        const long r = row0 + e / N;
+        if (r < n_rows) data[r * N + (e % N)] = buf[e];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// y pass: complex DFT along y of tiles (field, kx plane, z chunk), in place.
+// ----------------------------------------------------------------------------
+template <typename R, int N, int SIGN>
+__global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict__ data, long field_stride,
+                                               int n_planes, const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int TZ = Shape<R, N>::TZ;
+    constexpr int NZC = N / TZ;
+    constexpr int LS = N + 1;
+    constexpr int NT = 256;
+    __shared__ C buf[TZ * LS];
+    const int tid = threadIdx.x;
+    const long b = blockIdx.x;
+    const int zc = int(b % NZC);
+    const long fp = b / NZC;
+    const int kx = int(fp % n_planes);
+    const long f = fp / n_planes;
+    C* base = data + f * field_stride + long(kx) * N * N + zc * TZ;
+    for (int e = tid; e < TZ * N; e += NT) {
+        const int y = e / TZ, zz = e % TZ;
+        buf[zz * LS + y] = base[long(y) * N + zz];
+    }
+    __syncthreads();
+    lds_fft<C, N, TZ, NT, SIGN, LS, 1>(buf, tw, tid);
+    for (int e = tid; e < TZ * N; e += NT) {
+        const int y = e / TZ, zz = e % TZ;
+        base[long(y) * N + zz] = buf[zz * LS + y];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// x pass, real -> half (forward).  Tile (y, z chunk); z pairs (2p, 2p+1) ride
+// as the real and imaginary parts of one complex line.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_xpass_r2c(const R* __restrict__ in, typename CplxOf<R>::T* __restrict__ out,
+                                                   const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int TZ = Shape<R, N>::TZ;
+    constexpr int P = TZ / 2;
+    constexpr int NZC = N / TZ;
+    constexpr int H = N / 2 + 1;
+    constexpr int LS = N + 1;
+    constexpr int NT = 256;
+    __shared__ C buf[P * LS];
+    const int tid = threadIdx.x;
+    const int zc = blockIdx.x % NZC;
+    const int y = blockIdx.x / NZC;
+    const int z0 = zc * TZ;
+    const C* inc = reinterpret_cast<const C*>(in);
+    for (int e = tid; e < N * P; e += NT) {
+        const int x = e / P, p = e % P;
+        buf[p * LS + x] = inc[((long(x) * N + y) * N + z0) / 2 + p];
+    }
+    __syncthreads();
+    lds_fft<C, N, P, NT, -1, LS, 1>(buf, tw, tid);
+    for (int e = tid; e < H * P; e += NT) {
+        const int k = e / P, p = e % P;
+        const C zk = buf[p * LS + k];
+        const C zm = buf[p * LS + ((N - k) % N)];
+        const C a = cmk<C>(R(0.5) * (zk.x + zm.x), R(0.5) * (zk.y - zm.y));
+        const C bb = cmk<C>(R(0.5) * (zk.y + zm.y), R(-0.5) * (zk.x - zm.x));
+        C* o = out + (long(k) * N + y) * N + z0 + 2 * p;
+        o[0] = a;
+        o[1] = bb;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// x pass, half -> real (inverse).
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_xpass_c2r(const typename CplxOf<R>::T* __restrict__ in, R* __restrict__ out,
+                                                   const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int TZ = Shape<R, N>::TZ;
+    constexpr int P = TZ / 2;
+    constexpr int NZC = N / TZ;
+    constexpr int H = N / 2 + 1;
+    constexpr int LS = N + 1;
+    constexpr int NT = 256;
+    __shared__ C buf[P * LS];
+    const int tid = threadIdx.x;
+    const int zc = blockIdx.x % NZC;
+    const int y = blockIdx.x / NZC;
+    const int z0 = zc * TZ;
+    for (int e = tid; e < H * P; e += NT) {
+        const int k = e / P, p = e % P;
+        const C* src = in + (long(k) * N + y) * N + z0 + 2 * p;
+        C a = src[0], b = src[1];
+        if (k == 0 || k == N / 2) {
+            a.y = R(0);
+            b.y = R(0);
+        }
+        buf[p * LS + k] = cmk<C>(a.x - b.y, a.y + b.x);
+        if (k > 0 && k < N / 2) buf[p * LS + (N - k)] = cmk<C>(a.x + b.y, b.x - a.y);
+    }
+    __syncthreads();
+    lds_fft<C, N, P, NT, +1, LS, 1>(buf, tw, tid);
+    C* outc = reinterpret_cast<C*>(out);
+    for (int e = tid; e < N * P; e += NT) {
+        const int x = e / P, p = e % P;
+        outc[((long(x) * N + y) * N + z0) / 2 + p] = buf[p * LS + x];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Spectral filter and field maps.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_filter(typename CplxOf<R>::T* __restrict__ half, const double* __restrict__ amp) {
+    using C = typename CplxOf<R>::T;
+    constexpr long FS = Shape<R, N>::FS;
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= FS) return;
+    const int kz = int(i % N);
+    const int ky = int((i / N) % N);
+    const int kx = int(i / (long(N) * N));
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
+    const R a = (R)amp[nx * nx + ny * ny + nz * nz];
+    C v = half[i];
+    half[i] = cmk<C>(v.x * a, v.y * a);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sumsq_partial(const R* __restrict__ x, long total, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const long per = (total + gridDim.x - 1) / gridDim.x;
+    const long lo = long(blockIdx.x) * per;
+    const long hi = (lo + per < total) ? lo + per : total;
+    double acc = 0.0;
+    for (long i = lo + tid; i < hi; i += 256) {
+        const double v = (double)x[i];
+        acc += v * v;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int i = tid; i < n; i += 256) acc += part[i];
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = red[0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_map_scale(const R* __restrict__ in, R* __restrict__ out, long total,
+                                                   const double* __restrict__ sum_sq, MapParams mp, double scale) {
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= total) return;
+    const double zg = (double)in[i];
+    double z;
+    if (mp.kind == 1) {
+        const double m2 = sum_sq[0] / (double)total;
+        z = zg + mp.F_NL * (zg * zg - m2) + mp.G_NL * zg * zg * zg;
+    } else if (mp.kind == 2) {
+        double a = 1.0 - mp.beta * zg;
+        a = a > mp.clip ? a : mp.clip;
+        z = -log(a) / mp.beta;
+    } else {
+        z = zg;
+    }
+    out[i] = (R)(z * scale);
+}
+
+// ----------------------------------------------------------------------------
+// Per-target lookup tables over integer |n|^2.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_target, double k_lo, double k_hi,
+                                             const double* __restrict__ edges, int n_modes,
+                                             int16_t* __restrict__ lut_u, uint8_t* __restrict__ lut_shell) {
+    const int n2 = blockIdx.x * 256 + threadIdx.x;
+    if (n2 > n2max) return;
+    const double rt = sqrt((double)n2);
+    const double u = k_F * rt / k_target;
+    int idx = -1;
+    if (u >= edges[0] && u < edges[n_modes]) {
+        int lo = 0, hi = n_modes;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (edges[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        idx = lo;
+    }
+    lut_u[n2] = (int16_t)idx;
+    const double k = k_F * rt;
+    lut_shell[n2] = (n2 > 0 && k >= k_lo && k < k_hi) ? 1 : 0;
+}
+
+// ----------------------------------------------------------------------------
+// gen_z: Fourier weighting fused into the first inverse pass (along z).
+// Block = RBG rows (kx, ky).  For each kept term a: V = phi_a(u) Phi_hat / V,
+// fields i qt_j V (j = x, y, z), inverse DFT along z, stored to T.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __restrict__ phi_hat,
+                                               const int16_t* __restrict__ lut_u, const R* __restrict__ phi_tab,
+                                               int n_alpha, int a0, int na, R k_F, R inv_V,
+                                               typename CplxOf<R>::T* __restrict__ T,
+                                               const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int RB = Shape<R, N>::RBG_;
+    constexpr long FS = Shape<R, N>::FS;
+    constexpr int NT = 256;
+    constexpr int E = (RB * N + NT - 1) / NT;
+    constexpr int LS = N;
+    __shared__ C buf[3 * RB * LS];
+    const int tid = threadIdx.x;
+    const long row0 = long(blockIdx.x) * RB;
+    C ph[E];
+    int idx[E];
+    R q[E][3];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int e = tid + i * NT;
+        idx[i] = -1;
+        ph[i] = cmk<C>(R(0), R(0));
+        q[i][0] = q[i][1] = q[i][2] = R(0);
+        if (e < RB * N) {
+            const long r = row0 + e / N;
+            const int kz = e % N;
+            const int kx = int(r / N), ky = int(r % N);
+            const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
+            ph[i] = phi_hat[r * N + kz];
+            ph[i] = cmk<C>(ph[i].x * inv_V, ph[i].y * inv_V);
+            idx[i] = lut_u[nx * nx + ny * ny + nz * nz];
+            q[i][0] = (nx == -N / 2) ? R(0) : k_F * R(nx);
+            q[i][1] = (ny == -N / 2) ? R(0) : k_F * R(ny);
+            q[i][2] = (nz == -N / 2) ? R(0) : k_F * R(nz);
+        }
+    }
+    for (int a = a0; a < a0 + na; ++a) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int e = tid + i * NT;
+            if (e < RB * N) {
+                const int row = e / N, kz = e % N;
+                const R w = idx[i] >= 0 ? phi_tab[idx[i] * n_alpha + a] : R(0);
+                const C v = cmk<C>(ph[i].x * w, ph[i].y * w);
+                // i q v = (-q v.y, q v.x)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    buf[(j * RB + row) * LS + kz] = cmk<C>(-q[i][j] * v.y, q[i][j] * v.x);
+            }
+        }
+        __syncthreads();
+        lds_fft<C, N, 3 * RB, NT, +1, LS, 1>(buf, tw, tid);
+        const long fbase = long(3 * (a - a0)) * FS;
+        for (int e = tid; e < 3 * RB * N; e += NT) {
+            const int line = e / N, kz = e % N;
+            const int j = line / RB, row = line % RB;
+            T[fbase + long(j) * FS + (row0 + row) * N + kz] = buf[line * LS + kz];
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// xprod: last inverse pass (x, complex -> real) + products + first forward
+// pass (x, real -> complex).  Block = (y, z chunk of TZX).  Q stays in
+// registers across all kept terms.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __restrict__ T, const R* __restrict__ sigma,
+                                               int a0, int na, R dV, typename CplxOf<R>::T* __restrict__ Qx,
+                                               int n_planes, int accumulate,
+                                               const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    using S = Shape<R, N>;
+    constexpr int TZ = S::TZX;
+    constexpr int P = S::PX;
+    constexpr int NT = S::NTX;
+    constexpr int PP = S::PPX;
+    constexpr int NZC = N / TZ;
+    constexpr int H = N / 2 + 1;
+    constexpr long FS = S::FS;
+    constexpr int LS = N + 1;
+    __shared__ C Z[3 * P * LS];
+    const int tid = threadIdx.x;
+    const int zc = blockIdx.x % NZC;
+    const int y = blockIdx.x / NZC;
+    const int z0 = zc * TZ;
+    C Q[6][PP];
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int i = 0; i < PP; ++i) Q[c][i] = cmk<C>(R(0), R(0));
+
+    for (int a = a0; a < a0 + na; ++a) {
+        const long fb = long(3 * (a - a0)) * FS;
+        for (int e = tid; e < 3 * H * P; e += NT) {
+            const int j = e / (H * P);
+            const int rem = e - j * (H * P);
+            const int k = rem / P, p = rem % P;
+            const C* src = T + fb + long(j) * FS + (long(k) * N + y) * N + z0 + 2 * p;
+            C av = src[0], bv = src[1];
+            if (k == 0 || k == N / 2) {
+                av.y = R(0);
+                bv.y = R(0);
+            }
+            C* line = Z + (j * P + p) * LS;
+            line[k] = cmk<C>(av.x - bv.y, av.y + bv.x);
+            if (k > 0 && k < N / 2) line[N - k] = cmk<C>(av.x + bv.y, bv.x - av.y);
+        }
+        __syncthreads();
+        lds_fft<C, N, 3 * P, NT, +1, LS, 1>(Z, tw, tid);
+        const R s = sigma[a] * dV;
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int qq = tid + i * NT;
+            const int x = qq % N, p = qq / N;
+            const C gx = Z[(0 * P + p) * LS + x];
+            const C gy = Z[(1 * P + p) * LS + x];
+            const C gz = Z[(2 * P + p) * LS + x];
+            const C sx = cmk<C>(s * gx.x, s * gx.y);
+            const C sy = cmk<C>(s * gy.x, s * gy.y);
+            Q[0][i] = cmk<C>(Q[0][i].x + sx.x * gx.x, Q[0][i].y + sx.y * gx.y);
+            Q[1][i] = cmk<C>(Q[1][i].x + sy.x * gy.x, Q[1][i].y + sy.y * gy.y);
+            Q[2][i] = cmk<C>(Q[2][i].x + s * gz.x * gz.x, Q[2][i].y + s * gz.y * gz.y);
+            Q[3][i] = cmk<C>(Q[3][i].x + sx.x * gy.x, Q[3][i].y + sx.y * gy.y);
+            Q[4][i] = cmk<C>(Q[4][i].x + sx.x * gz.x, Q[4][i].y + sx.y * gz.y);
+            Q[5][i] = cmk<C>(Q[5][i].x + sy.x * gz.x, Q[5][i].y + sy.y * gz.y);
+        }
+        __syncthreads();
+    }
+    // forward DFT along x of the six components, three at a time
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int qq = tid + i * NT;
+            const int x = qq % N, p = qq / N;
+#pragma unroll
+            for (int cl = 0; cl < 3; ++cl) Z[(cl * P + p) * LS + x] = Q[3 * h + cl][i];
+        }
+        __syncthreads();
+        lds_fft<C, N, 3 * P, NT, -1, LS, 1>(Z, tw, tid);
+        for (int e = tid; e < 3 * H * P; e += NT) {
+            const int cl = e / (H * P);
+            const int rem = e - cl * (H * P);
+            const int k = rem / P, p = rem % P;
+            if (k < n_planes) {
+                const C* line = Z + (cl * P + p) * LS;
+                const C zk = line[k];
+                const C zm = line[(N - k) % N];
+                const C A = cmk<C>(R(0.5) * (zk.x + zm.x), R(0.5) * (zk.y - zm.y));
+                const C B = cmk<C>(R(0.5) * (zk.y + zm.y), R(-0.5) * (zk.x - zm.x));
+                C* o = Qx + long(3 * h + cl) * FS + (long(k) * N + y) * N + z0 + 2 * p;
+                if (accumulate) {
+                    const C oa = o[0], ob = o[1];
+                    o[0] = cadd(oa, A);
+                    o[1] = cadd(ob, B);
+                } else {
+                    o[0] = A;
+                    o[1] = B;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// zbin: last forward pass (z) of the 12 components + TT projection + FP64
+// shell sums.  Block = RBB rows (kx, ky); rows that cannot reach the shell
+// are skipped.  Q_hat component order per kernel: xx, yy, zz, xy, xz, yz.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double tt_power(const double2* X /* 6 comps */, double kx, double ky, double kz) {
+    // Y = P X P with P = 1 - k k^T; returns sum |Y_ij|^2 - |tr Y|^2 / 2.
+    const double k[3] = {kx, ky, kz};
+    double2 M[3][3];
+    M[0][0] = X[0]; M[1][1] = X[1]; M[2][2] = X[2];
+    M[0][1] = M[1][0] = X[3];
+    M[0][2] = M[2][0] = X[4];
+    M[1][2] = M[2][1] = X[5];
+    double2 a[3];   // a = X k
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        a[i].x = M[i][0].x * k[0] + M[i][1].x * k[1] + M[i][2].x * k[2];
+        a[i].y = M[i][0].y * k[0] + M[i][1].y * k[1] + M[i][2].y * k[2];
+    }
+    double2 beta;   // k^T X k
+    beta.x = k[0] * a[0].x + k[1] * a[1].x + k[2] * a[2].x;
+    beta.y = k[0] * a[0].y + k[1] * a[1].y + k[2] * a[2].y;
+    double s = 0.0;
+    double2 tr;
+    tr.x = 0.0;
+    tr.y = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            // Y_ij = X_ij - k_i a_j - a_i k_j + beta k_i k_j
+            double yr = M[i][j].x - k[i] * a[j].x - a[i].x * k[j] + beta.x * k[i] * k[j];
+            double yi = M[i][j].y - k[i] * a[j].y - a[i].y * k[j] + beta.y * k[i] * k[j];
+            s += yr * yr + yi * yi;
+            if (i == j) {
+                tr.x += yr;
+                tr.y += yi;
+            }
+        }
+    }
+    return s - 0.5 * (tr.x * tr.x + tr.y * tr.y);
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __restrict__ Qxy,
+                                              const uint8_t* __restrict__ lut_shell, int n2_lo, int n2_hi,
+                                              double* __restrict__ part_sum,
+                                              unsigned long long* __restrict__ part_cnt,
+                                              const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int RB = Shape<R, N>::RBB_;
+    constexpr long FS = Shape<R, N>::FS;
+    constexpr int NT = 256;
+    constexpr int LS = N;
+    __shared__ C buf[12 * RB * LS];
+    __shared__ double rsum[NT / 64];
+    __shared__ unsigned long long rcnt[NT / 64];
+    const int tid = threadIdx.x;
+    const long row0 = long(blockIdx.x) * RB;
+    // can any row of this block reach the shell?
+    bool any = false;
+    for (int r = 0; r < RB; ++r) {
+        const long rr = row0 + r;
+        const int kx = int(rr / N), ky = int(rr % N);
+        const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+        const int mn = nx * nx + ny * ny;
+        const int mx = mn + (N / 2) * (N / 2);
+        if (mn <= n2_hi && mx >= n2_lo) any = true;
+    }
+    double acc = 0.0;
+    unsigned long long cnt = 0ull;
+    if (any) {
+        for (int e = tid; e < 12 * RB * N; e += NT) {
+            const int line = e / N, kz = e % N;
+            const int comp = line / RB, row = line % RB;
+            buf[line * LS + kz] = Qxy[long(comp) * FS + (row0 + row) * N + kz];
+        }
+        __syncthreads();
+        lds_fft<C, N, 12 * RB, NT, -1, LS, 1>(buf, tw, tid);
+        for (int e = tid; e < RB * N; e += NT) {
+            const int row = e / N, kz = e % N;
+            const long rr = row0 + row;
+            const int kx = int(rr / N), ky = int(rr % N);
+            const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
+            const int n2 = nx * nx + ny * ny + nz * nz;
+            if (n2 < n2_lo || n2 > n2_hi || !lut_shell[n2]) continue;
+            const double inv = 1.0 / sqrt((double)n2);
+            const double khx = nx * inv, khy = ny * inv, khz = nz * inv;
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                double2 X[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const C v = buf[((m * 6 + c) * RB + row) * LS + kz];
+                    X[c].x = (double)v.x;
+                    X[c].y = (double)v.y;
+                }
+                s += tt_power(X, khx, khy, khz);
+            }
+            const int w = (kx == 0 || kx == N / 2) ? 1 : 2;
+            acc += w * s;
+            cnt += (unsigned long long)w;
+        }
+    }
+    // block reduction in a fixed order: wave shuffles, then the waves in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_down(acc, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) {
+        rsum[wv] = acc;
+        rcnt[wv] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        unsigned long long c = 0ull;
+        for (int i = 0; i < NT / 64; ++i) {
+            t += rsum[i];
+            c += rcnt[i];
+        }
+        part_sum[blockIdx.x] = t;
+        part_cnt[blockIdx.x] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ ps, const unsigned long long* __restrict__ pc,
+                                                  int n, double* __restrict__ out_sum,
+                                                  unsigned long long* __restrict__ out_cnt) {
+    __shared__ double rs[256];
+    __shared__ unsigned long long rc[256];
+    const int tid = threadIdx.x;
+    double a = 0.0;
+    unsigned long long c = 0ull;
+    for (int i = tid; i < n; i += 256) {
+        a += ps[i];
+        c += pc[i];
+    }
+    rs[tid] = a;
+    rc[tid] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            rs[tid] += rs[tid + s];
+            rc[tid] += rc[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out_sum[0] = rs[0];
+        out_cnt[0] = rc[0];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Engine specialisation
+// ----------------------------------------------------------------------------
+template <typename R, int NN> struct EngineImpl final : Engine {
+    using C = typename CplxOf<R>::T;
+    using S = Shape<R, NN>;
+    const C* tw;
+    explicit EngineImpl(const void* twd) : tw(static_cast<const C*>(twd)) {}
+
+    int N() const override { return NN; }
+    size_t real_bytes() const override { return sizeof(R); }
+    size_t complex_bytes() const override { return sizeof(C); }
+    int zbin_blocks() const override { return int((long(S::H) * NN) / S::RBB_); }
+    int sumsq_blocks() const override { return 1024; }
+
+    void noise(uint64_t seed, void* out, hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_noise<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(static_cast<R*>(out), total, seed);
+    }
+    void xpass_r2c(const void* in, void* out, hipStream_t s) override {
+        k_xpass_r2c<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(256), 0, s>>>(static_cast<const R*>(in),
+                                                                      static_cast<C*>(out), tw);
+    }
+    void xpass_c2r(const void* in, void* out, hipStream_t s) override {
+        k_xpass_c2r<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(256), 0, s>>>(static_cast<const C*>(in),
+                                                                      static_cast<R*>(out), tw);
+    }
+    void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign, hipStream_t s) override {
+        const unsigned blocks = unsigned(long(n_fields) * n_planes * (NN / S::TZ));
+        if (blocks == 0) return;
+        if (sign < 0)
+            k_ypass<R, NN, -1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+        else
+            k_ypass<R, NN, +1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+    }
+    void zpass(void* data, long n_rows, int sign, hipStream_t s) override {
+        const unsigned blocks = unsigned((n_rows + S::RBZ_ - 1) / S::RBZ_);
+        if (blocks == 0) return;
+        if (sign < 0)
+            k_zpass<R, NN, -1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), n_rows, tw);
+        else
+            k_zpass<R, NN, +1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), n_rows, tw);
+    }
+    void filter(void* half, const double* amp, hipStream_t s) override {
+        k_filter<R, NN><<<dim3(unsigned((S::FS + 255) / 256)), dim3(256), 0, s>>>(static_cast<C*>(half), amp);
+    }
+    void sumsq(const void* real, double* partials, double* out, hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_sumsq_partial<R><<<dim3(1024), dim3(256), 0, s>>>(static_cast<const R*>(real), total, partials);
+        k_reduce_sum<<<dim3(1), dim3(256), 0, s>>>(partials, 1024, out);
+    }
+    void map_scale(const void* in, void* out, const double* sum_sq, const MapParams& mp, double scale,
+                   hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_map_scale<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(
+            static_cast<const R*>(in), static_cast<R*>(out), total, sum_sq, mp, scale);
+    }
+    void lut(double k_F, double k_target, double k_lo, double k_hi, const double* edges, int n_modes,
+             int16_t* lut_u, uint8_t* lut_shell, hipStream_t s) override {
+        const int n2max = S::N2MAX;
+        k_lut<<<dim3(unsigned(n2max / 256 + 1)), dim3(256), 0, s>>>(n2max, k_F, k_target, k_lo, k_hi, edges,
+                                                                    n_modes, lut_u, lut_shell);
+    }
+    void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab, int n_alpha, int a0, int na,
+               double k_F, double inv_V, void* T, hipStream_t s) override {
+        const unsigned blocks = unsigned((long(S::H) * NN) / S::RBG_);
+        k_gen_z<R, NN><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<const C*>(phi_hat), lut_u,
+                                                        static_cast<const R*>(phi_tab), n_alpha, a0, na,
+                                                        R(k_F), R(inv_V), static_cast<C*>(T), tw);
+    }
+    void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, void* Qx, int n_planes,
+               int accumulate, hipStream_t s) override {
+        const unsigned blocks = unsigned(NN * (NN / S::TZX));
+        k_xprod<R, NN><<<dim3(blocks), dim3(S::NTX), 0, s>>>(static_cast<const C*>(T),
+                                                           static_cast<const R*>(sigma_tab), a0, na, R(dV),
+                                                           static_cast<C*>(Qx), n_planes, accumulate, tw);
+    }
+    void zbin(const void* Qxy, const uint8_t* lut_shell, int n2_lo, int n2_hi, double* ps,
+              unsigned long long* pc, hipStream_t s) override {
+        k_zbin<R, NN><<<dim3(unsigned(zbin_blocks())), dim3(256), 0, s>>>(static_cast<const C*>(Qxy), lut_shell,
+                                                                         n2_lo, n2_hi, ps, pc, tw);
+    }
+    void finalize(const double* ps, const unsigned long long* pc, int n, double* out_sum,
+                  unsigned long long* out_cnt, hipStream_t s) override {
+        k_finalize<<<dim3(1), dim3(256), 0, s>>>(ps, pc, n, out_sum, out_cnt);
+    }
+};
+
+template <typename R> static Engine* make_for(int N, const void* tw) {
+    switch (N) {
+        case 8: return new EngineImpl<R, 8>(tw);
+        case 16: return new EngineImpl<R, 16>(tw);
+        case 32: return new EngineImpl<R, 32>(tw);
+        case 64: return new EngineImpl<R, 64>(tw);
+        case 128: return new EngineImpl<R, 128>(tw);
+        case 256: return new EngineImpl<R, 256>(tw);
+        case 384: return new EngineImpl<R, 384>(tw);
+        case 512: return new EngineImpl<R, 512>(tw);
+        default: return nullptr;
+    }
+}
+
+Engine* make_engine(int prec, int N, const void* tw) {
+    return prec == 1 ? make_for<double>(N, tw) : make_for<float>(N, tw);
+}
+
+void host_twiddles(int prec, int N, void* out) {
+    for (int t = 0; t < N; ++t) {
+        // exp(-2 pi i t / N) from an exactly reduced angle
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)N;
+        const long double c = cosl(a), s = sinl(a);
+        if (prec == 1) {
+            static_cast<double*>(out)[2 * t] = (double)c;
+            static_cast<double*>(out)[2 * t + 1] = (double)s;
+        } else {
+            static_cast<float*>(out)[2 * t] = (float)c;
+            static_cast<float*>(out)[2 * t + 1] = (float)s;
+        }
+    }
+}
+
+}  // namespace sigw

@@ -1,0 +1,821 @@
+// Host side of the C ABI: argument validation, the separable kernel tables of
+// Sec. V (u-grid, kernel matrix, symmetric eigen-decomposition), plan memory,
+// and the enqueue order of the per-target kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/sigw.h"
+#include "sigw_engine.hpp"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool supported_N(int N) {
+    switch (N) {
+        case 8: case 16: case 32: case 64: case 128: case 256: case 384: case 512: return true;
+        default: return false;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sec. V, Eq. grid_density: cumulative of rho(u) = 1 + A_p exp(-(u-u_p)^2/(2 sigma_p^2)).
+// ---------------------------------------------------------------------------
+double grid_cumulative(double u, const sigw_plan_desc& d) {
+    const double s2 = std::sqrt(2.0) * d.sigma_p;
+    return (u - d.u_min) + d.A_p * d.sigma_p * std::sqrt(kPi / 2.0) *
+                               (std::erf((u - d.u_p) / s2) - std::erf((d.u_min - d.u_p) / s2));
+}
+
+// Edges e_n = n^{-1}(n), n = 0..n_modes: each is the smallest double where the
+// normalised cumulative reaches n (bisection down to adjacent doubles).
+std::vector<double> grid_edges(const sigw_plan_desc& d) {
+    const int M = d.n_modes;
+    std::vector<double> e(M + 1);
+    const double total = grid_cumulative(d.u_max, d);
+    e[0] = d.u_min;
+    e[M] = d.u_max;
+    for (int n = 1; n < M; ++n) {
+        const double target = total * n / M;
+        double lo = d.u_min, hi = d.u_max;
+        for (;;) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (grid_cumulative(mid, d) < target) lo = mid;
+            else hi = mid;
+        }
+        e[n] = hi;
+    }
+    return e;
+}
+
+// Eq. kernels.
+double kernel_s(double u, double v) {
+    const double a = u * u + v * v - 3.0;
+    if (!(u + v > std::sqrt(3.0))) return 0.0;
+    return 27.0 * kPi * a * a / (32.0 * u * u * u * v * v * v);
+}
+double kernel_c(double u, double v) {
+    const double a = u * u + v * v - 3.0;
+    const double lg = std::log(std::fabs((3.0 - (u + v) * (u + v)) / (3.0 - (u - v) * (u - v))));
+    return 27.0 * a / (32.0 * u * u * u * v * v * v) * (-4.0 * u * v + a * lg);
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major).
+// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
+void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
+    V.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+    auto v = [&](int i, int j) -> double& { return V[size_t(i) * n + j]; };
+    double norm2 = 0.0;
+    for (size_t i = 0; i < A.size(); ++i) norm2 += A[i] * A[i];
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += a(p, q) * a(p, q);
+        if (off <= 1e-34 * norm2) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a(p, q);
+                if (apq == 0.0) continue;
+                const double app = a(p, p), aqq = a(q, q);
+                if (std::fabs(apq) < 1e-300) {
+                    a(p, q) = a(q, p) = 0.0;
+                    continue;
+                }
+                // rotation that zeroes A_pq: t = tan(phi), the smaller root of t^2 + 2 theta t - 1 = 0
+                const double theta = (aqq - app) / (2.0 * apq);
+                double t = 1.0 / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                if (theta < 0.0) t = -t;
+                const double c = 1.0 / std::sqrt(t * t + 1.0);
+                const double s = t * c;
+                const double tau = s / (1.0 + c);
+                a(p, p) = app - t * apq;
+                a(q, q) = aqq + t * apq;
+                a(p, q) = a(q, p) = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    if (r == p || r == q) continue;
+                    const double g = a(r, p), h = a(r, q);
+                    a(r, p) = a(p, r) = g - s * (h + g * tau);
+                    a(r, q) = a(q, r) = h + s * (g - h * tau);
+                }
+                for (int r = 0; r < n; ++r) {
+                    const double g = v(r, p), h = v(r, q);
+                    v(r, p) = g - s * (h + g * tau);
+                    v(r, q) = h + s * (g - h * tau);
+                }
+            }
+        }
+    }
+}
+
+struct Table {
+    std::vector<double> sigma;   // n_alpha
+    std::vector<double> phi;     // n_modes x n_alpha
+};
+
+// Sec. V: C_ij = sqrt(L_i L_j) I(c_i, c_j) on |c_i - c_j| <= 1 <= c_i + c_j
+// (the triangle u, v and the unit k close), diagonalised; the n_alpha terms
+// of largest |sigma| are kept with their signs; phi_a = q_a,i / sqrt(L_i).
+Table build_table(const sigw_plan_desc& d, const std::vector<double>& e, int m) {
+    const int M = d.n_modes;
+    std::vector<double> c(M), L(M);
+    for (int i = 0; i < M; ++i) {
+        c[i] = 0.5 * (e[i] + e[i + 1]);
+        L[i] = e[i + 1] - e[i];
+    }
+    std::vector<double> A(size_t(M) * M, 0.0);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            const double u = c[i], v = c[j];
+            if (std::fabs(u - v) <= 1.0 && u + v >= 1.0)
+                A[size_t(i) * M + j] = std::sqrt(L[i] * L[j]) * (m == 0 ? kernel_s(u, v) : kernel_c(u, v));
+        }
+    std::vector<double> V;
+    jacobi_eigen(A, V, M);
+    std::vector<int> order(M);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return std::fabs(A[size_t(x) * M + x]) > std::fabs(A[size_t(y) * M + y]);
+    });
+    Table t;
+    t.sigma.resize(d.n_alpha);
+    t.phi.assign(size_t(M) * d.n_alpha, 0.0);
+    for (int a = 0; a < d.n_alpha; ++a) {
+        const int k = order[a];
+        t.sigma[a] = A[size_t(k) * M + k];
+        for (int i = 0; i < M; ++i) t.phi[size_t(i) * d.n_alpha + a] = V[size_t(i) * M + k] / std::sqrt(L[i]);
+    }
+    return t;
+}
+
+const char* validate(const sigw_plan_desc* d) {
+    if (!d) return "NULL plan description";
+    if (!supported_N(d->N)) return "N must be one of 8, 16, 32, 64, 128, 256, 384, 512";
+    if (!(d->L > 0.0) || !std::isfinite(d->L)) return "L must be positive and finite";
+    if (d->prec != SIGW_F32 && d->prec != SIGW_F64) return "prec must be SIGW_F32 or SIGW_F64";
+    if (d->n_slots < 1 || d->n_slots > 4096) return "n_slots must be in [1, 4096]";
+    if (d->n_modes < 2 || d->n_modes > 4096) return "n_modes must be in [2, 4096]";
+    if (d->n_alpha < 1 || d->n_alpha > d->n_modes) return "n_alpha must be in [1, n_modes]";
+    if (!(d->u_min > 0.0) || !(d->u_max > d->u_min) || !std::isfinite(d->u_max))
+        return "need 0 < u_min < u_max";
+    if (!(d->sigma_p > 0.0) || !(d->A_p >= 0.0) || !std::isfinite(d->u_p)) return "need sigma_p > 0, A_p >= 0";
+    if (d->alpha_chunk < 0 || d->alpha_chunk > d->n_alpha) return "alpha_chunk must be in [0, n_alpha]";
+    return nullptr;
+}
+
+struct Sizes {
+    long H, FS, R3, n2max;
+    size_t cb, rb;
+    int chunk;
+};
+
+Sizes sizes_of(const sigw_plan_desc& d) {
+    Sizes z;
+    z.H = d.N / 2 + 1;
+    z.FS = z.H * d.N * long(d.N);
+    z.R3 = long(d.N) * d.N * d.N;
+    z.n2max = 3L * (d.N / 2) * (d.N / 2);
+    z.rb = d.prec == SIGW_F64 ? 8 : 4;
+    z.cb = 2 * z.rb;
+    z.chunk = d.alpha_chunk == 0 ? d.n_alpha : d.alpha_chunk;
+    return z;
+}
+
+constexpr int kMaxTargets = 4096;
+constexpr int kSumsqBlocks = 1024;
+
+size_t footprint_of(const sigw_plan_desc& d) {
+    const Sizes z = sizes_of(d);
+    const int zb = int(z.H * d.N);   // upper bound on zbin partials
+    size_t b = 0;
+    b += size_t(d.N) * z.cb;                                   // twiddles
+    b += size_t(d.n_modes + 1) * 8;                            // edges
+    b += 2 * size_t(d.n_modes) * d.n_alpha * z.rb + 2 * size_t(d.n_alpha) * z.rb;
+    b += size_t(z.n2max + 1) * (2 + 1 + 8);                    // lut_u, lut_shell, amp
+    b += size_t(d.n_slots) * z.FS * z.cb;                      // Phi_hat per slot
+    b += size_t(3) * z.chunk * z.FS * z.cb;                    // gradient-field workspace
+    b += size_t(12) * z.FS * z.cb;                             // Q components (both kernels)
+    b += size_t(z.R3) * z.rb;                                  // real scratch
+    b += size_t(zb) * 16 + size_t(kSumsqBlocks + 1) * 8;       // partials
+    b += size_t(kMaxTargets) * 16;                             // per-target sums
+    return b;
+}
+
+const char* kTimedNames[] = {"gen_z", "ypass", "xprod", "ypass_q", "zbin"};
+constexpr int kNumTimed = 5;
+
+}  // namespace
+
+struct sigw_plan {
+    sigw_plan_desc d{};
+    Sizes z{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::unique_ptr<sigw::Engine> eng;
+    std::string err;
+    std::vector<double> edges_h;
+    Table tab_h[2];
+    // device buffers
+    void* tw = nullptr;
+    double* edges = nullptr;
+    void* phi_tab[2] = {nullptr, nullptr};
+    void* sigma_tab[2] = {nullptr, nullptr};
+    int16_t* lut_u = nullptr;
+    uint8_t* lut_shell = nullptr;
+    double* amp = nullptr;
+    void* phi_hat = nullptr;
+    void* T = nullptr;
+    void* Q = nullptr;
+    void* real = nullptr;
+    double* part_sum = nullptr;
+    unsigned long long* part_cnt = nullptr;
+    double* sq_part = nullptr;
+    double* sums = nullptr;
+    unsigned long long* cnts = nullptr;
+    // pinned host staging: results, and the spectral amplitude table of the
+    // last field generation (guarded by amp_ev until its copy has run)
+    double* h_amp = nullptr;
+    hipEvent_t amp_ev = nullptr;
+    bool amp_inflight = false;
+    double* h_sums = nullptr;
+    unsigned long long* h_cnts = nullptr;
+    std::vector<char> has_field;
+    // async spectrum state
+    hipEvent_t done_ev = nullptr;
+    bool pending = false;
+    std::vector<double> pend_targets;
+    std::vector<int> pend_valid;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;   // (kernel id, start event index)
+    double t_sum[kNumTimed] = {0, 0, 0, 0, 0};
+    long t_cnt[kNumTimed] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+sigw_status fail(sigw_plan* p, sigw_status s, const std::string& msg) {
+    if (p) p->err = msg;
+    return s;
+}
+
+#define HIP_TRY(p, call)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((p), SIGW_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+char* cplx_at(void* base, long elems, size_t cb) { return static_cast<char*>(base) + size_t(elems) * cb; }
+
+// Event-bracketed launch when timing is on.
+template <typename F> sigw_status timed(sigw_plan* p, int id, F&& launch) {
+    if (!p->timing) {
+        launch();
+        return SIGW_OK;
+    }
+    while (p->ev_pool.size() < p->ev_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(p, hipEventCreate(&e));
+        p->ev_pool.push_back(e);
+    }
+    const size_t i0 = p->ev_used;
+    HIP_TRY(p, hipEventRecord(p->ev_pool[i0], p->stream));
+    launch();
+    HIP_TRY(p, hipEventRecord(p->ev_pool[i0 + 1], p->stream));
+    p->ev_used += 2;
+    p->ev_marks.push_back({id, i0});
+    return SIGW_OK;
+}
+
+// After the stream is synchronised: fold the bracketed times into the totals.
+sigw_status collect_times(sigw_plan* p) {
+    for (auto& m : p->ev_marks) {
+        float ms = 0.f;
+        HIP_TRY(p, hipEventElapsedTime(&ms, p->ev_pool[m.second], p->ev_pool[m.second + 1]));
+        p->t_sum[m.first] += ms;
+        p->t_cnt[m.first] += 1;
+    }
+    p->ev_marks.clear();
+    p->ev_used = 0;
+    return SIGW_OK;
+}
+
+// Integer |n|^2 range of the shell k_lo <= k_F sqrt(n2) < k_hi, n2 > 0, using
+// the same FP64 expression as the device lookup table.
+bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n2_hi) {
+    auto inside = [&](long n2) {
+        const double k = kF * std::sqrt((double)n2);
+        return n2 > 0 && k >= lo && k < hi;
+    };
+    if (!(hi > lo)) return false;
+    double a = lo / kF;
+    long start = std::max(1L, (long)std::floor(a * a) - 2);
+    long first = -1;
+    for (long n2 = start; n2 <= n2max; ++n2) {
+        const double k = kF * std::sqrt((double)n2);
+        if (k >= hi) break;
+        if (inside(n2)) {
+            first = n2;
+            break;
+        }
+    }
+    if (first < 0) return false;
+    double b = hi / kF;
+    long last = std::min(n2max, (long)std::ceil(b * b) + 2);
+    while (last >= first && !inside(last)) --last;
+    if (last < first) return false;
+    // every integer in [first, last] satisfies the monotone predicate
+    *n2_lo = int(first);
+    *n2_hi = int(last);
+    return true;
+}
+
+// Enqueue the convolutions of one target for one slot, leaving the 12
+// components after the forward y pass in p->Q (planes [0, n_planes)).
+sigw_status enqueue_convolutions(sigw_plan* p, int slot, double k_target, int n_planes) {
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    const double kF = 2.0 * kPi / d.L;
+    const double V = d.L * d.L * d.L;
+    const double dV = V / double(z.R3);
+    const void* ph = cplx_at(p->phi_hat, long(slot) * z.FS, z.cb);
+    for (int m = 0; m < 2; ++m) {
+        void* Qm = cplx_at(p->Q, long(m) * 6 * z.FS, z.cb);
+        for (int a0 = 0; a0 < d.n_alpha; a0 += z.chunk) {
+            const int na = std::min(z.chunk, d.n_alpha - a0);
+            sigw_status s;
+            s = timed(p, 0, [&] {
+                p->eng->gen_z(ph, p->lut_u, p->phi_tab[m], d.n_alpha, a0, na, kF, 1.0 / V, p->T, p->stream);
+            });
+            if (s) return s;
+            s = timed(p, 1, [&] { p->eng->ypass(p->T, 3 * na, z.FS, int(z.H), +1, p->stream); });
+            if (s) return s;
+            s = timed(p, 2, [&] {
+                p->eng->xprod(p->T, p->sigma_tab[m], a0, na, dV, Qm, n_planes, a0 > 0 ? 1 : 0, p->stream);
+            });
+            if (s) return s;
+        }
+    }
+    return timed(p, 3, [&] { p->eng->ypass(p->Q, 12, z.FS, n_planes, -1, p->stream); });
+}
+
+sigw_status check_launch(sigw_plan* p) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(p, SIGW_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return SIGW_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+sigw_status check_targets(sigw_plan* p, int n_k, const double* kt, const double* lo, const double* hi) {
+    if (n_k < 0 || n_k > kMaxTargets) return fail(p, SIGW_E_INVALID, "n_k must be in [0, 4096]");
+    if (n_k > 0 && (!kt || !lo || !hi)) return fail(p, SIGW_E_INVALID, "NULL target or shell array");
+    for (int b = 0; b < n_k; ++b) {
+        if (!finite_pos(kt[b])) return fail(p, SIGW_E_INVALID, "targets must be positive and finite");
+        if (!std::isfinite(lo[b]) || !std::isfinite(hi[b]) || !(hi[b] > lo[b]))
+            return fail(p, SIGW_E_INVALID, "each shell needs k_lo < k_hi, both finite");
+    }
+    return SIGW_OK;
+}
+
+// Enqueue lut + convolutions + zbin + finalize of targets [0, n_k) for one
+// slot; sums/cnts land at device offset `out0`.  valid[b] = 0 marks an empty shell.
+sigw_status enqueue_spectrum(sigw_plan* p, int slot, int n_k, const double* kt, const double* lo,
+                             const double* hi, int out0, std::vector<int>& valid) {
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    const double kF = 2.0 * kPi / d.L;
+    valid.assign(n_k, 0);
+    for (int b = 0; b < n_k; ++b) {
+        int n2_lo = 0, n2_hi = -1;
+        if (!shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi)) continue;
+        valid[b] = 1;
+        const int kxm = std::min(d.N / 2, (int)std::floor(std::sqrt((double)n2_hi)));
+        const int n_planes = kxm + 1;
+        p->eng->lut(kF, kt[b], lo[b], hi[b], p->edges, d.n_modes, p->lut_u, p->lut_shell, p->stream);
+        sigw_status s = enqueue_convolutions(p, slot, kt[b], n_planes);
+        if (s) return s;
+        s = timed(p, 4, [&] {
+            p->eng->zbin(p->Q, p->lut_shell, n2_lo, n2_hi, p->part_sum, p->part_cnt, p->stream);
+        });
+        if (s) return s;
+        p->eng->finalize(p->part_sum, p->part_cnt, p->eng->zbin_blocks(), p->sums + out0 + b,
+                         p->cnts + out0 + b, p->stream);
+    }
+    return check_launch(p);
+}
+
+void to_omega(const sigw_plan* p, int n_k, const double* kt, const double* S, const unsigned long long* C,
+              const int* valid, double* omega, int64_t* nmodes) {
+    const double V = p->d.L * p->d.L * p->d.L;
+    for (int b = 0; b < n_k; ++b) {
+        const bool ok = valid[b] && C[b] > 0;
+        // Omega_b = k^3/(48 pi^2 V N_b) * (16/k^4) S_b, the 16/k^4 from X = -+(4/k^2) Q_hat
+        if (omega) omega[b] = ok ? S[b] / (3.0 * kPi * kPi * kt[b] * V * double(C[b])) : 0.0;
+        if (nmodes) nmodes[b] = ok ? int64_t(C[b]) : 0;
+    }
+}
+
+sigw_status check_slot(sigw_plan* p, int slot, bool need_field) {
+    if (slot < 0 || slot >= p->d.n_slots) return fail(p, SIGW_E_INVALID, "slot out of range");
+    if (need_field && !p->has_field[slot]) return fail(p, SIGW_E_STATE, "no field in this slot yet");
+    return SIGW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sigw_status_string(sigw_status s) {
+    switch (s) {
+        case SIGW_OK: return "ok";
+        case SIGW_E_INVALID: return "invalid argument";
+        case SIGW_E_NOMEM: return "out of device memory";
+        case SIGW_E_DEVICE: return "device error";
+        case SIGW_E_UNSUPPORTED: return "unsupported";
+        case SIGW_E_STATE: return "call out of order";
+        case SIGW_E_PENDING: return "pending";
+    }
+    return "unknown status";
+}
+
+const char* sigw_last_error(sigw_plan_t p) { return p ? p->err.c_str() : ""; }
+
+sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32_t prec) {
+    if (!d) return SIGW_E_INVALID;
+    std::memset(d, 0, sizeof(*d));
+    d->N = N;
+    d->L = L;
+    d->prec = prec;
+    d->n_slots = 1;
+    d->n_modes = 200;
+    d->n_alpha = 50;
+    d->u_min = 1e-3;
+    d->u_max = 15.0;
+    d->u_p = 1.0;
+    d->sigma_p = 0.5;
+    d->A_p = 10.0;
+    d->alpha_chunk = 0;
+    return SIGW_OK;
+}
+
+sigw_status sigw_plan_footprint(const sigw_plan_desc* d, size_t* bytes) {
+    if (validate(d) || !bytes) return SIGW_E_INVALID;
+    *bytes = footprint_of(*d);
+    return SIGW_OK;
+}
+
+sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma, double* phi, double* edges) {
+    if (validate(d) || (m != 0 && m != 1)) return SIGW_E_INVALID;
+    try {
+        std::vector<double> e = grid_edges(*d);
+        if (edges) std::copy(e.begin(), e.end(), edges);
+        if (sigma || phi) {
+            Table t = build_table(*d, e, m);
+            if (sigma) std::copy(t.sigma.begin(), t.sigma.end(), sigma);
+            if (phi) std::copy(t.phi.begin(), t.phi.end(), phi);
+        }
+    } catch (const std::bad_alloc&) {
+        return SIGW_E_NOMEM;
+    }
+    return SIGW_OK;
+}
+
+sigw_status sigw_plan_destroy(sigw_plan_t p) {
+    if (!p) return SIGW_E_INVALID;
+    (void)hipStreamSynchronize(p->stream);
+    void* bufs[] = {p->tw, p->edges, p->phi_tab[0], p->phi_tab[1], p->sigma_tab[0], p->sigma_tab[1],
+                    p->lut_u, p->lut_shell, p->amp, p->phi_hat, p->T, p->Q, p->real, p->part_sum,
+                    p->part_cnt, p->sq_part, p->sums, p->cnts};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (p->h_amp) (void)hipHostFree(p->h_amp);
+    if (p->amp_ev) (void)hipEventDestroy(p->amp_ev);
+    if (p->h_sums) (void)hipHostFree(p->h_sums);
+    if (p->h_cnts) (void)hipHostFree(p->h_cnts);
+    if (p->done_ev) (void)hipEventDestroy(p->done_ev);
+    for (auto e : p->ev_pool) (void)hipEventDestroy(e);
+    delete p;
+    return SIGW_OK;
+}
+
+sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_plan_t* out) {
+    if (!out) return SIGW_E_INVALID;
+    *out = nullptr;
+    if (const char* why = validate(d)) {
+        (void)why;
+        return SIGW_E_INVALID;
+    }
+    std::unique_ptr<sigw_plan> p(new (std::nothrow) sigw_plan());
+    if (!p) return SIGW_E_NOMEM;
+    p->d = *d;
+    p->z = sizes_of(*d);
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->has_field.assign(d->n_slots, 0);
+    // Sec. V tables on the host
+    try {
+        p->edges_h = grid_edges(*d);
+        for (int m = 0; m < 2; ++m) p->tab_h[m] = build_table(*d, p->edges_h, m);
+    } catch (const std::bad_alloc&) {
+        return SIGW_E_NOMEM;
+    }
+    for (int m = 0; m < 2; ++m)
+        for (double s : p->tab_h[m].sigma)
+            if (!std::isfinite(s)) return SIGW_E_INVALID;
+    sigw_plan* P = p.get();
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return SIGW_E_DEVICE;
+    if (hipGetDevice(&P->device) != hipSuccess) return SIGW_E_DEVICE;
+    const Sizes& z = P->z;
+    auto alloc = [&](void** ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            return false;
+        }
+        return true;
+    };
+    const int zb_max = int(z.H * d->N);
+    bool ok = alloc(&P->tw, size_t(d->N) * z.cb) && alloc((void**)&P->edges, (d->n_modes + 1) * 8) &&
+              alloc(&P->phi_tab[0], size_t(d->n_modes) * d->n_alpha * z.rb) &&
+              alloc(&P->phi_tab[1], size_t(d->n_modes) * d->n_alpha * z.rb) &&
+              alloc(&P->sigma_tab[0], size_t(d->n_alpha) * z.rb) && alloc(&P->sigma_tab[1], size_t(d->n_alpha) * z.rb) &&
+              alloc((void**)&P->lut_u, size_t(z.n2max + 1) * 2) && alloc((void**)&P->lut_shell, size_t(z.n2max + 1)) &&
+              alloc((void**)&P->amp, size_t(z.n2max + 1) * 8) &&
+              alloc(&P->phi_hat, size_t(d->n_slots) * z.FS * z.cb) &&
+              alloc(&P->T, size_t(3) * z.chunk * z.FS * z.cb) && alloc(&P->Q, size_t(12) * z.FS * z.cb) &&
+              alloc(&P->real, size_t(z.R3) * z.rb) && alloc((void**)&P->part_sum, size_t(zb_max) * 8) &&
+              alloc((void**)&P->part_cnt, size_t(zb_max) * 8) &&
+              alloc((void**)&P->sq_part, size_t(kSumsqBlocks + 1) * 8) &&
+              alloc((void**)&P->sums, size_t(kMaxTargets) * 8) && alloc((void**)&P->cnts, size_t(kMaxTargets) * 8);
+    if (!ok) {
+        sigw_plan_destroy(p.release());
+        return SIGW_E_NOMEM;
+    }
+    if (hipHostMalloc((void**)&P->h_sums, kMaxTargets * 8) != hipSuccess ||
+        hipHostMalloc((void**)&P->h_cnts, kMaxTargets * 8) != hipSuccess ||
+        hipHostMalloc((void**)&P->h_amp, size_t(z.n2max + 1) * 8) != hipSuccess ||
+        hipEventCreate(&P->amp_ev) != hipSuccess || hipEventCreate(&P->done_ev) != hipSuccess) {
+        sigw_plan_destroy(p.release());
+        return SIGW_E_DEVICE;
+    }
+    // tables: twiddles, edges, phi, sigma (in the path precision)
+    std::vector<char> twh(size_t(d->N) * z.cb);
+    sigw::host_twiddles(d->prec, d->N, twh.data());
+    std::vector<char> phih[2], sigh[2];
+    for (int m = 0; m < 2; ++m) {
+        const Table& t = P->tab_h[m];
+        phih[m].resize(t.phi.size() * z.rb);
+        sigh[m].resize(t.sigma.size() * z.rb);
+        for (size_t i = 0; i < t.phi.size(); ++i) {
+            if (d->prec == SIGW_F64) reinterpret_cast<double*>(phih[m].data())[i] = t.phi[i];
+            else reinterpret_cast<float*>(phih[m].data())[i] = (float)t.phi[i];
+        }
+        for (size_t i = 0; i < t.sigma.size(); ++i) {
+            if (d->prec == SIGW_F64) reinterpret_cast<double*>(sigh[m].data())[i] = t.sigma[i];
+            else reinterpret_cast<float*>(sigh[m].data())[i] = (float)t.sigma[i];
+        }
+    }
+    bool up = hipMemcpy(P->tw, twh.data(), twh.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(P->edges, P->edges_h.data(), P->edges_h.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    for (int m = 0; m < 2 && up; ++m)
+        up = hipMemcpy(P->phi_tab[m], phih[m].data(), phih[m].size(), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(P->sigma_tab[m], sigh[m].data(), sigh[m].size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!up) {
+        sigw_plan_destroy(p.release());
+        return SIGW_E_DEVICE;
+    }
+    P->eng.reset(sigw::make_engine(d->prec, d->N, P->tw));
+    if (!P->eng) {
+        sigw_plan_destroy(p.release());
+        return SIGW_E_UNSUPPORTED;
+    }
+    *out = p.release();
+    return SIGW_OK;
+}
+
+sigw_status sigw_white_noise(sigw_plan_t p, uint64_t seed, void* out_dev) {
+    if (!p || !out_dev) return fail(p, SIGW_E_INVALID, "NULL argument");
+    p->eng->noise(seed, out_dev, p->stream);
+    return check_launch(p);
+}
+
+namespace {
+// Phi_hat[slot] = dV DFT(scale * map(real)); real holds zeta_g on entry.
+sigw_status finish_field(sigw_plan* p, int slot, const sigw::MapParams& mp, bool reduce) {
+    const Sizes& z = p->z;
+    const double V = p->d.L * p->d.L * p->d.L;
+    const double dV = V / double(z.R3);
+    if (reduce) p->eng->sumsq(p->real, p->sq_part, p->sq_part + kSumsqBlocks, p->stream);
+    p->eng->map_scale(p->real, p->real, p->sq_part + kSumsqBlocks, mp, (2.0 / 3.0) * dV, p->stream);
+    void* dst = cplx_at(p->phi_hat, long(slot) * z.FS, z.cb);
+    p->eng->xpass_r2c(p->real, dst, p->stream);
+    p->eng->ypass(dst, 1, z.FS, int(z.H), -1, p->stream);
+    p->eng->zpass(dst, z.H * p->d.N, -1, p->stream);
+    sigw_status s = check_launch(p);
+    if (s == SIGW_OK) p->has_field[slot] = 1;
+    return s;
+}
+}  // namespace
+
+sigw_status sigw_generate_field(sigw_plan_t p, int32_t slot, uint64_t seed, const sigw_lognormal* sp,
+                                const sigw_ngmap* mp) {
+    if (!p || !sp || !mp) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (sigw_status s = check_slot(p, slot, false)) return s;
+    if (!(sp->A >= 0.0) || !finite_pos(sp->sigma) || !finite_pos(sp->k_star) || !std::isfinite(sp->A))
+        return fail(p, SIGW_E_INVALID, "log-normal needs A >= 0, sigma > 0, k_star > 0");
+    if (mp->kind < 0 || mp->kind > 2) return fail(p, SIGW_E_INVALID, "unknown map kind");
+    if (mp->kind == 2 && (!finite_pos(mp->beta) || !finite_pos(mp->clip)))
+        return fail(p, SIGW_E_INVALID, "exponential tail needs beta > 0 and clip > 0");
+    if (mp->kind == 1 && (!std::isfinite(mp->F_NL) || !std::isfinite(mp->G_NL)))
+        return fail(p, SIGW_E_INVALID, "local map needs finite F_NL, G_NL");
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    const double kF = 2.0 * kPi / d.L;
+    const double V = d.L * d.L * d.L;
+    const double dV = V / double(z.R3);
+    // amplitude per |n|^2: sqrt(dV P(k_F |n|)) / V, zero at n = 0 (the 1/V is the
+    // inverse-transform normalisation of zeta_g(x) = (1/V) sum exp(iqx) zeta_hat)
+    if (p->amp_inflight) {
+        HIP_TRY(p, hipEventSynchronize(p->amp_ev));   // the previous table's copy has run
+        p->amp_inflight = false;
+    }
+    double* amp = p->h_amp;
+    amp[0] = 0.0;
+    for (long n2 = 1; n2 <= z.n2max; ++n2) {
+        const double k = kF * std::sqrt((double)n2);
+        const double lk = std::log(k / sp->k_star);
+        const double d2 = sp->A / std::sqrt(2.0 * kPi * sp->sigma * sp->sigma) *
+                          std::exp(-lk * lk / (2.0 * sp->sigma * sp->sigma));
+        const double P = 2.0 * kPi * kPi * d2 / (k * k * k);
+        amp[n2] = std::sqrt(dV * P) / V;
+    }
+    HIP_TRY(p, hipMemcpyAsync(p->amp, amp, size_t(z.n2max + 1) * 8, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipEventRecord(p->amp_ev, p->stream));
+    p->amp_inflight = true;
+    void* half = p->Q;   // scratch half spectrum
+    p->eng->noise(seed, p->real, p->stream);
+    p->eng->xpass_r2c(p->real, half, p->stream);
+    p->eng->ypass(half, 1, z.FS, int(z.H), -1, p->stream);
+    p->eng->zpass(half, z.H * d.N, -1, p->stream);
+    p->eng->filter(half, p->amp, p->stream);
+    p->eng->zpass(half, z.H * d.N, +1, p->stream);
+    p->eng->ypass(half, 1, z.FS, int(z.H), +1, p->stream);
+    p->eng->xpass_c2r(half, p->real, p->stream);
+    sigw::MapParams m{mp->kind, mp->F_NL, mp->G_NL, mp->beta, mp->clip};
+    return finish_field(p, slot, m, mp->kind == 1);
+}
+
+sigw_status sigw_set_zeta(sigw_plan_t p, int32_t slot, const void* zeta_dev) {
+    if (!p || !zeta_dev) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (sigw_status s = check_slot(p, slot, false)) return s;
+    HIP_TRY(p, hipMemcpyAsync(p->real, zeta_dev, size_t(p->z.R3) * p->z.rb, hipMemcpyDeviceToDevice, p->stream));
+    sigw::MapParams m{0, 0, 0, 0, 0};
+    return finish_field(p, slot, m, false);
+}
+
+sigw_status sigw_set_phi_hat(sigw_plan_t p, int32_t slot, const void* src) {
+    if (!p || !src) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (sigw_status s = check_slot(p, slot, false)) return s;
+    HIP_TRY(p, hipMemcpyAsync(cplx_at(p->phi_hat, long(slot) * p->z.FS, p->z.cb), src, size_t(p->z.FS) * p->z.cb,
+                              hipMemcpyDeviceToDevice, p->stream));
+    p->has_field[slot] = 1;
+    return SIGW_OK;
+}
+
+sigw_status sigw_get_phi_hat(sigw_plan_t p, int32_t slot, void* dst) {
+    if (!p || !dst) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (sigw_status s = check_slot(p, slot, true)) return s;
+    HIP_TRY(p, hipMemcpyAsync(dst, cplx_at(p->phi_hat, long(slot) * p->z.FS, p->z.cb), size_t(p->z.FS) * p->z.cb,
+                              hipMemcpyDeviceToDevice, p->stream));
+    return SIGW_OK;
+}
+
+sigw_status sigw_source_convolutions(sigw_plan_t p, int32_t slot, double k_target, void* qhat_dev) {
+    if (!p || !qhat_dev) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (!finite_pos(k_target)) return fail(p, SIGW_E_INVALID, "k_target must be positive");
+    if (sigw_status s = check_slot(p, slot, true)) return s;
+    const Sizes& z = p->z;
+    const double kF = 2.0 * kPi / p->d.L;
+    p->eng->lut(kF, k_target, 0.0, 0.0, p->edges, p->d.n_modes, p->lut_u, p->lut_shell, p->stream);
+    if (sigw_status s = enqueue_convolutions(p, slot, k_target, int(z.H))) return s;
+    p->eng->zpass(p->Q, 12 * z.H * p->d.N, -1, p->stream);
+    HIP_TRY(p, hipMemcpyAsync(qhat_dev, p->Q, size_t(12) * z.FS * z.cb, hipMemcpyDeviceToDevice, p->stream));
+    return check_launch(p);
+}
+
+sigw_status sigw_spectrum_batch(sigw_plan_t p, int32_t n_sel, const int32_t* slots, int32_t n_k, const double* kt,
+                                const double* lo, const double* hi, double* omega, int64_t* nmodes) {
+    if (!p) return SIGW_E_INVALID;
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    if (n_sel < 1 || !slots) return fail(p, SIGW_E_INVALID, "need at least one slot");
+    if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
+    if (long(n_sel) * n_k > kMaxTargets) return fail(p, SIGW_E_INVALID, "n_sel * n_k exceeds 4096");
+    for (int i = 0; i < n_sel; ++i)
+        if (sigw_status s = check_slot(p, slots[i], true)) return s;
+    std::vector<int> valid;
+    for (int i = 0; i < n_sel; ++i) {
+        if (sigw_status s = enqueue_spectrum(p, slots[i], n_k, kt, lo, hi, i * n_k, valid)) return s;
+    }
+    const size_t cnt = size_t(n_sel) * n_k;
+    if (cnt) {
+        HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, cnt * 8, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(p, hipMemcpyAsync(p->h_cnts, p->cnts, cnt * 8, hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (p->timing) {
+        if (sigw_status s = collect_times(p)) return s;
+    }
+    for (int i = 0; i < n_sel; ++i)
+        to_omega(p, n_k, kt, p->h_sums + i * n_k, p->h_cnts + i * n_k, valid.data(),
+                 omega ? omega + size_t(i) * n_k : nullptr, nmodes ? nmodes + size_t(i) * n_k : nullptr);
+    return SIGW_OK;
+}
+
+sigw_status sigw_spectrum(sigw_plan_t p, int32_t slot, int32_t n_k, const double* kt, const double* lo,
+                          const double* hi, double* omega, int64_t* nmodes) {
+    return sigw_spectrum_batch(p, 1, &slot, n_k, kt, lo, hi, omega, nmodes);
+}
+
+sigw_status sigw_spectrum_enqueue(sigw_plan_t p, int32_t slot, int32_t n_k, const double* kt, const double* lo,
+                                  const double* hi) {
+    if (!p) return SIGW_E_INVALID;
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is already in flight");
+    if (n_k > 64) return fail(p, SIGW_E_INVALID, "asynchronous spectra take at most 64 targets");
+    if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
+    if (sigw_status s = check_slot(p, slot, true)) return s;
+    if (sigw_status s = enqueue_spectrum(p, slot, n_k, kt, lo, hi, 0, p->pend_valid)) return s;
+    if (n_k) {
+        HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(p, hipMemcpyAsync(p->h_cnts, p->cnts, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(p, hipEventRecord(p->done_ev, p->stream));
+    p->pend_targets.assign(kt, kt + n_k);
+    p->pending = true;
+    return SIGW_OK;
+}
+
+sigw_status sigw_spectrum_poll(sigw_plan_t p, double* omega, int64_t* nmodes) {
+    if (!p) return SIGW_E_INVALID;
+    if (!p->pending) return fail(p, SIGW_E_STATE, "no asynchronous spectrum in flight");
+    hipError_t e = hipEventQuery(p->done_ev);
+    if (e == hipErrorNotReady) return SIGW_E_PENDING;
+    if (e != hipSuccess) {
+        p->pending = false;
+        return fail(p, SIGW_E_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e));
+    }
+    p->pending = false;
+    if (p->timing) {
+        if (sigw_status s = collect_times(p)) return s;
+    }
+    const int n_k = int(p->pend_targets.size());
+    to_omega(p, n_k, p->pend_targets.data(), p->h_sums, p->h_cnts, p->pend_valid.data(), omega, nmodes);
+    return SIGW_OK;
+}
+
+sigw_status sigw_synchronize(sigw_plan_t p) {
+    if (!p) return SIGW_E_INVALID;
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return SIGW_OK;
+}
+
+sigw_status sigw_set_timing(sigw_plan_t p, int32_t enabled) {
+    if (!p) return SIGW_E_INVALID;
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    p->timing = enabled != 0;
+    for (int i = 0; i < kNumTimed; ++i) {
+        p->t_sum[i] = 0;
+        p->t_cnt[i] = 0;
+    }
+    p->ev_marks.clear();
+    p->ev_used = 0;
+    return SIGW_OK;
+}
+
+sigw_status sigw_kernel_time(sigw_plan_t p, const char* name, double* avg_ms, int64_t* launches) {
+    if (!p || !name) return SIGW_E_INVALID;
+    for (int i = 0; i < kNumTimed; ++i) {
+        if (std::strcmp(name, kTimedNames[i]) == 0) {
+            if (avg_ms) *avg_ms = p->t_cnt[i] ? p->t_sum[i] / double(p->t_cnt[i]) : 0.0;
+            if (launches) *launches = p->t_cnt[i];
+            return SIGW_OK;
+        }
+    }
+    return fail(p, SIGW_E_INVALID, "unknown kernel name");
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+"""Write FP64 oracle values for the full-size parity tests (sampled bins).
+
+    python tests/golden/make_golden.py [name ...]
+
+Calls only the oracle and the workload recipes; the GPU path never writes
+anything here.  Each fixture records the workload, the sampled targets and
+the oracle's Omega and mode counts per target.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import decomposition, field, spectrum  # noqa: E402
+
+
+def _job_dict(job):
+    return {"N": job.N, "L": job.L, "A": job.spectrum.A, "sigma": job.spectrum.sigma,
+            "k_star": job.spectrum.k_star, "map": job.ngmap.kind, "F_NL": job.ngmap.F_NL,
+            "G_NL": job.ngmap.G_NL, "beta": job.ngmap.beta, "clip": job.ngmap.clip}
+
+
+def sampled(job, seeds_bins, name, note):
+    tabs = decomposition.tables()
+    out = {"name": name, "note": note, "job": _job_dict(job), "samples": [],
+           "generated_by": "python tests/golden/make_golden.py " + name}
+    for seed, bins in seeds_bins:
+        t0 = time.time()
+        ph = field.phi_hat(job.N, job.L, seed, job.spectrum, job.ngmap)
+        for b in bins:
+            om, nb = spectrum.omega_target(ph, tabs[0], tabs[1], job.targets[b], job.k_lo[b],
+                                           job.k_hi[b], job.L)
+            out["samples"].append({"seed": seed, "bin": int(b), "target": float(job.targets[b]),
+                                   "k_lo": float(job.k_lo[b]), "k_hi": float(job.k_hi[b]),
+                                   "omega": float(om), "nmodes": int(nb)})
+            print(name, seed, b, om, nb, f"{time.time() - t0:.0f}s", flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+FIXTURES = {
+    # 256^3 local NG (f_NL = 5), 64 log bins, seeds 0..3: low tail, rise, peak, high tail
+    "local256_fp64_oracle": lambda: sampled(
+        W.config_local_ng(256, 64), [(0, [20, 33, 44, 60]), (3, [44])], "local256_fp64_oracle",
+        "256^3 local NG f_NL=5 (F_NL=3), A=1e-2, sigma=0.5, k*=20, 64 log bins; FP64 oracle"),
+}
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(FIXTURES)
+    for n in names:
+        FIXTURES[n]()

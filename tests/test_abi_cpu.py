@@ -1,0 +1,98 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/sigw.h declares, and its host-only logic (argument validation, the
+Sec. V kernel tables, the footprint formula) is correct.  No compute call is
+made here: there is no GPU on this machine.
+
+P6 (library side): the library's own grid + Jacobi eigen-decomposition gives
+the same kept kernel sum_a sigma_a phi_a phi_a as the oracle's NumPy eigh,
+to 1e-12 relative, for both kernels.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_27231_amd as P
+from paper_2605_27231_amd import _lib
+from oracle import decomposition
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sigw.h")).read()
+    return sorted(set(re.findall(r"\b(sigw_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_status_strings():
+    L = _lib.lib()
+    assert L.sigw_status_string(0) == b"ok"
+    assert L.sigw_status_string(-1) == b"invalid argument"
+
+
+def test_desc_default_and_validation():
+    L = _lib.lib()
+    d = _lib.PlanDesc()
+    assert L.sigw_plan_desc_default(ct.byref(d), 256, 6.283185307179586, 0) == 0
+    assert (d.n_modes, d.n_alpha, d.u_min, d.u_max, d.u_p, d.sigma_p, d.A_p) == \
+        (200, 50, 1e-3, 15.0, 1.0, 0.5, 10.0)
+    out = ct.c_void_p()
+    bad = []
+    for field, val in (("N", 100), ("N", 0), ("L", -1.0), ("prec", 3), ("n_slots", 0),
+                       ("n_alpha", 201), ("n_alpha", 0), ("u_min", 0.0), ("u_max", 1e-4),
+                       ("sigma_p", 0.0), ("alpha_chunk", 51)):
+        dd = P.plan_desc(64)
+        setattr(dd, field, val)
+        bad.append(L.sigw_plan_create(ct.byref(dd), None, ct.byref(out)))
+        assert out.value is None
+    assert all(b == _lib.SIGW_E_INVALID for b in bad), bad
+    assert L.sigw_plan_create(None, None, ct.byref(out)) == _lib.SIGW_E_INVALID
+    size = ct.c_size_t()
+    assert L.sigw_plan_footprint(None, ct.byref(size)) == _lib.SIGW_E_INVALID
+    # NULL plan handles are rejected, not dereferenced
+    assert L.sigw_spectrum(None, 0, 0, None, None, None, None, None) == _lib.SIGW_E_INVALID
+    assert L.sigw_synchronize(None) == _lib.SIGW_E_INVALID
+    assert L.sigw_plan_destroy(None) == _lib.SIGW_E_INVALID
+
+
+def test_footprint_formula():
+    for N, prec, cb in ((64, "f32", 8), (256, "f32", 8), (256, "f64", 16), (512, "f32", 8)):
+        d = P.plan_desc(N, prec=prec)
+        fs = (N // 2 + 1) * N * N
+        main = (1 + 150 + 12) * fs * cb + N ** 3 * cb // 2
+        got = P.sigw_plan_footprint(d)
+        assert main <= got <= main * 1.01 + 4e6, (N, prec, got, main)
+    # fewer terms per pass shrink the workspace
+    assert P.sigw_plan_footprint(P.plan_desc(256, alpha_chunk=10)) < \
+        P.sigw_plan_footprint(P.plan_desc(256)) / 3
+
+
+@pytest.mark.parametrize("m", [0, 1])
+def test_library_kernel_table_matches_oracle(m):
+    tab = decomposition.tables()[m]
+    s, phi, e = P.sigw_kernel_table(P.plan_desc(32), m)
+    assert np.max(np.abs(e - tab.edges)) <= 4e-16 * np.max(tab.edges)
+    np.testing.assert_allclose(s, tab.sigma, rtol=1e-12)
+    K_lib = (phi * s) @ phi.T
+    K_or = (tab.phi * tab.sigma) @ tab.phi.T
+    assert np.max(np.abs(K_lib - K_or)) <= 1e-12 * np.max(np.abs(K_or))
+
+
+def test_library_kernel_table_other_meta_parameters():
+    d = P.plan_desc(32, n_modes=120, n_alpha=30, u_p=0.8, A_p=5.0)
+    tab = decomposition.decompose("c", n_modes=120, n_alpha=30, u_p=0.8, A_p=5.0)
+    s, phi, e = P.sigw_kernel_table(d, 1)
+    K_lib = (phi * s) @ phi.T
+    K_or = (tab.phi * tab.sigma) @ tab.phi.T
+    assert np.max(np.abs(K_lib - K_or)) <= 1e-12 * np.max(np.abs(K_or))
