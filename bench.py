@@ -72,15 +72,21 @@ def run_gpu(args):
             lat.append(time.perf_counter() - t0)
         return om, nb
 
-    for _ in range(args.warmup):
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        tw = time.perf_counter()
         step([])
+        say(f"warmup step {i} {time.perf_counter() - tw:.2f}s")
     torch.cuda.synchronize()
     plan.set_timing(True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         om, nb = step(lat)
+        say(f"timed step {i} done at {time.perf_counter() - t0:.2f}s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_spectra = len(seeds) * args.steps
@@ -184,6 +190,7 @@ def main():
     g = run_gpu(args)
     cpu = None
     if not args.no_cpu:
+        print("[bench] oracle CPU baseline sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
     line = {
         "metric": "Omega_GW spectra/s (256^3 FP32 fields/FFT, FP64 shell sums)",

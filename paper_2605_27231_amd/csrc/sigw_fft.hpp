@@ -168,4 +168,175 @@ __device__ __forceinline__ void lds_fft(C* buf, const C* __restrict__ tw, int ti
     stockham_from<C, N, NL, NT, SIGN, LS, ES, 0, 1>(buf, tw, tid);
 }
 
+
+// ----------------------------------------------------------------------------
+// Register DFTs of composite size (four-step inside one thread).
+// Twiddles come from the length-N table tw[t] = exp(-2 pi i t / N) at
+// compile-time offsets, so they are uniform (scalar) loads.
+// ----------------------------------------------------------------------------
+template <int R> struct RegSplit;                 // R = F * G, F a base radix
+template <> struct RegSplit<12> { static constexpr int F = 4, G = 3; };
+template <> struct RegSplit<16> { static constexpr int F = 4, G = 4; };
+template <> struct RegSplit<24> { static constexpr int F = 8, G = 3; };
+template <> struct RegSplit<32> { static constexpr int F = 8, G = 4; };
+
+template <int SIGN, int N, typename C>
+__device__ __forceinline__ C tw_at(const C* __restrict__ tw, int e) {
+    C w = tw[e];
+    if (SIGN > 0) w.y = -w.y;
+    return w;
+}
+
+template <int R, int SIGN, int N, typename C>
+__device__ __forceinline__ void reg_dft(C* a, const C* __restrict__ tw) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2 || R == 3 || R == 4 || R == 8) {
+        dft<R, SIGN>(a);
+    } else {
+        constexpr int F = RegSplit<R>::F;
+        constexpr int G = RegSplit<R>::G;
+        static_assert(F * G == R, "bad split");
+        static_assert(N % R == 0, "register DFT size must divide N");
+        C tmp[R];
+        // x index n = g + G f; out index k = kf + F kg
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            C v[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) v[f] = a[g + G * f];
+            dft<F, SIGN>(v);
+#pragma unroll
+            for (int kf = 0; kf < F; ++kf) {
+                if (g * kf == 0) tmp[g * F + kf] = v[kf];
+                else tmp[g * F + kf] = cmul(v[kf], tw_at<SIGN, N>(tw, ((g * kf) % R) * (N / R)));
+            }
+        }
+#pragma unroll
+        for (int kf = 0; kf < F; ++kf) {
+            C w[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) w[g] = tmp[g * F + kf];
+            reg_dft<G, SIGN, N>(w, tw);
+#pragma unroll
+            for (int kg = 0; kg < G; ++kg) a[kf + F * kg] = w[kg];
+        }
+    }
+}
+
+// Factorisation N = R1 * R2 used by the two-phase line transform.
+template <int N> struct TwoPhase;
+template <> struct TwoPhase<8> { static constexpr int R1 = 2; };
+template <> struct TwoPhase<16> { static constexpr int R1 = 4; };
+template <> struct TwoPhase<32> { static constexpr int R1 = 4; };
+template <> struct TwoPhase<64> { static constexpr int R1 = 8; };
+template <> struct TwoPhase<128> { static constexpr int R1 = 8; };
+template <> struct TwoPhase<256> { static constexpr int R1 = 16; };
+template <> struct TwoPhase<384> { static constexpr int R1 = 16; };
+template <> struct TwoPhase<512> { static constexpr int R1 = 16; };
+
+// ----------------------------------------------------------------------------
+// Two-phase transform of NL lines of length N = R1 R2 (four-step):
+//   phase 1, item (line, t), t < R2:  a_k1 = W_N^{t k1} sum_m x[t + R2 m] W_R1^{m k1}
+//   LDS transpose
+//   phase 2, item (line, k1), k1 < R1: X[k1 + R1 k2] = sum_t a_k1(t) W_R2^{t k2}
+// ld(line, n) supplies x; st(line, k, X) consumes the output.  LINE_FAST puts
+// consecutive threads on consecutive lines (for tiles whose lines are
+// interleaved in memory); otherwise consecutive threads walk along a line.
+// lds must hold NL * N complex (plus NL * R1 for the !LINE_FAST padding).
+// The routine starts and ends without a barrier of its own on the LDS
+// buffer other than the one between the phases; the caller synchronises
+// before lds is reused.
+// ----------------------------------------------------------------------------
+template <int N, int NL, bool LINE_FAST> struct TPLayout {
+    static constexpr int R1 = TwoPhase<N>::R1;
+    static constexpr int R2 = N / R1;
+    static constexpr int size = LINE_FAST ? NL * N : NL * R1 * (R2 + 1);
+    __device__ static __forceinline__ int at(int line, int k1, int t) {
+        return LINE_FAST ? (k1 * R2 + t) * NL + line : (line * R1 + k1) * (R2 + 1) + t;
+    }
+};
+
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
+__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, int tid) {
+    using Lay = TPLayout<N, NL, LINE_FAST>;
+    constexpr int R1 = Lay::R1, R2 = Lay::R2;
+    constexpr int ITEMS = NL * R2;
+#pragma unroll
+    for (int w0 = 0; w0 < ITEMS; w0 += NT) {
+        const int w = w0 + tid;
+        if ((ITEMS % NT == 0) || w < ITEMS) {
+            const int line = LINE_FAST ? w % NL : w / R2;
+            const int t = LINE_FAST ? w / NL : w % R2;
+            C a[R1];
+#pragma unroll
+            for (int m = 0; m < R1; ++m) a[m] = ld(line, t + R2 * m);
+            reg_dft<R1, SIGN, N>(a, tw);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                C v = a[k1];
+                if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(tw, t * k1));
+                lds[Lay::at(line, k1, t)] = v;
+            }
+        }
+    }
+}
+
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class ST>
+__device__ __forceinline__ void tp_phase2(ST&& st, const C* lds, const C* __restrict__ tw, int tid) {
+    using Lay = TPLayout<N, NL, LINE_FAST>;
+    constexpr int R1 = Lay::R1, R2 = Lay::R2;
+    constexpr int ITEMS = NL * R1;
+#pragma unroll
+    for (int w0 = 0; w0 < ITEMS; w0 += NT) {
+        const int w = w0 + tid;
+        if ((ITEMS % NT == 0) || w < ITEMS) {
+            const int line = LINE_FAST ? w % NL : w / R1;
+            const int k1 = LINE_FAST ? w / NL : w % R1;
+            C b[R2];
+#pragma unroll
+            for (int t = 0; t < R2; ++t) b[t] = lds[Lay::at(line, k1, t)];
+            reg_dft<R2, SIGN, N>(b, tw);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) st(line, k1 + R1 * k2, b[k2]);
+        }
+    }
+}
+
+// Phase 2 into registers: out[i][k2] for the i-th item of this thread
+// (item w = tid + i NT), so that the caller can synchronise before storing
+// into the same LDS buffer.
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST>
+struct TPRegs {
+    using Lay = TPLayout<N, NL, LINE_FAST>;
+    static constexpr int R1 = Lay::R1, R2 = Lay::R2;
+    static constexpr int ITEMS = NL * R1;
+    static constexpr int PER = (ITEMS + NT - 1) / NT;
+    C v[PER][R2];
+    __device__ __forceinline__ void run(const C* lds, const C* __restrict__ tw, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int w = tid + i * NT;
+            if ((ITEMS % NT == 0) || w < ITEMS) {
+                const int line = LINE_FAST ? w % NL : w / R1;
+                const int k1 = LINE_FAST ? w / NL : w % R1;
+#pragma unroll
+                for (int t = 0; t < R2; ++t) v[i][t] = lds[Lay::at(line, k1, t)];
+                reg_dft<R2, SIGN, N>(v[i], tw);
+            }
+        }
+    }
+    template <class ST> __device__ __forceinline__ void store(ST&& st, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int w = tid + i * NT;
+            if ((ITEMS % NT == 0) || w < ITEMS) {
+                const int line = LINE_FAST ? w % NL : w / R1;
+                const int k1 = LINE_FAST ? w / NL : w % R1;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) st(line, k1 + R1 * k2, v[i][k2]);
+            }
+        }
+    }
+};
+
 }  // namespace sigw

@@ -179,41 +179,70 @@ __global__ __launch_bounds__(256) void k_noise(R* __restrict__ out, long total, 
 }
 
 // ----------------------------------------------------------------------------
-// z pass: complex DFT along contiguous rows, in place.
+// Pass tiles.  Every transform below is the two-phase register FFT of
+// sigw_fft.hpp: one register DFT of size R1, one LDS transpose, one register
+// DFT of size R2 (N = R1 R2).
 // ----------------------------------------------------------------------------
+template <int N> struct TPConst {
+    static constexpr int R1 = TwoPhase<N>::R1;
+    static constexpr int R2 = N / R1;
+    static constexpr int RMIN = R1 < R2 ? R1 : R2;
+    static constexpr int RMAX = R1 > R2 ? R1 : R2;
+};
+
+template <int A, int B> struct CMin { static constexpr int v = A < B ? A : B; };
+template <int A, int B> struct CMax { static constexpr int v = A > B ? A : B; };
+constexpr int pow2_floor(long x) {
+    int p = 1;
+    while (2L * p <= x) p *= 2;
+    return p;
+}
+
+// z pass: complex DFT along contiguous rows, in place.  RB rows per block.
+template <typename R, int N> struct ZCfg {
+    using C = typename CplxOf<R>::T;
+    static constexpr int NT = 256;
+    static constexpr int RB0 = CMax<1, NT / TPConst<N>::RMIN>::v;
+    // keep the transpose tile at or below 64 KB (a power of two, so it divides N)
+    static constexpr long ROWB = long(TPLayout<N, 1, false>::size) * long(sizeof(C));
+    static constexpr int RB = pow2_floor(RB0 * ROWB > 65536 ? 65536 / ROWB : RB0);
+};
+
 template <typename R, int N, int SIGN>
 __global__ __launch_bounds__(256) void k_zpass(typename CplxOf<R>::T* __restrict__ data, long n_rows,
                                                const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
-    constexpr int RB = Shape<R, N>::RBZ_;
-    constexpr int NT = 256;
-    __shared__ C buf[RB * N];
+    constexpr int RB = ZCfg<R, N>::RB;
+    constexpr int NT = ZCfg<R, N>::NT;
+    __shared__ C lds[TPLayout<N, RB, false>::size];
     const int tid = threadIdx.x;
     const long row0 = long(blockIdx.x) * RB;
-    for (int e = tid; e < RB * N; e += NT) {
-        const long r = row0 + e / N;
-        buf[e] = (r < n_rows) ? data[r * N + (e % N)] : cmk<C>(R(0), R(0));
-    }
+    C* base = data + row0 * N;
+    auto ld = [&](int line, int n) -> C {
+        return (row0 + line < n_rows) ? base[long(line) * N + n] : cmk<C>(R(0), R(0));
+    };
+    auto st = [&](int line, int k, C v) {
+        if (row0 + line < n_rows) base[long(line) * N + k] = v;
+    };
+    tp_phase1<C, N, SIGN, RB, NT, false>(ld, lds, tw, tid);
     __syncthreads();
-    lds_fft<C, N, RB, NT, SIGN, N, 1>(buf, tw, tid);
-    for (int e = tid; e < RB * N; e += NT) {
-        const long r = row0 + e / N;
-        if (r < n_rows) data[r * N + (e % N)] = buf[e];
-    }
+    tp_phase2<C, N, SIGN, RB, NT, false>(st, lds, tw, tid);
 }
 
-// ----------------------------------------------------------------------------
 // y pass: complex DFT along y of tiles (field, kx plane, z chunk), in place.
-// ----------------------------------------------------------------------------
+template <typename R, int N> struct YCfg {
+    static constexpr int TZ = Shape<R, N>::TZ;
+    static constexpr int NT = CMin<256, CMax<64, TZ * TPConst<N>::RMIN>::v>::v;
+};
+
 template <typename R, int N, int SIGN>
 __global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict__ data, long field_stride,
                                                int n_planes, const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
-    constexpr int TZ = Shape<R, N>::TZ;
+    constexpr int TZ = YCfg<R, N>::TZ;
+    constexpr int NT = YCfg<R, N>::NT;
     constexpr int NZC = N / TZ;
-    constexpr int LS = N + 1;
-    constexpr int NT = 256;
-    __shared__ C buf[TZ * LS];
+    __shared__ C lds[TPLayout<N, TZ, true>::size];
     const int tid = threadIdx.x;
     const long b = blockIdx.x;
     const int zc = int(b % NZC);
@@ -221,48 +250,48 @@ __global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict
     const int kx = int(fp % n_planes);
     const long f = fp / n_planes;
     C* base = data + f * field_stride + long(kx) * N * N + zc * TZ;
-    for (int e = tid; e < TZ * N; e += NT) {
-        const int y = e / TZ, zz = e % TZ;
-        buf[zz * LS + y] = base[long(y) * N + zz];
-    }
+    auto ld = [&](int zz, int y) -> C { return base[long(y) * N + zz]; };
+    auto st = [&](int zz, int y, C v) { base[long(y) * N + zz] = v; };
+    tp_phase1<C, N, SIGN, TZ, NT, true>(ld, lds, tw, tid);
     __syncthreads();
-    lds_fft<C, N, TZ, NT, SIGN, LS, 1>(buf, tw, tid);
-    for (int e = tid; e < TZ * N; e += NT) {
-        const int y = e / TZ, zz = e % TZ;
-        base[long(y) * N + zz] = buf[zz * LS + y];
-    }
+    tp_phase2<C, N, SIGN, TZ, NT, true>(st, lds, tw, tid);
 }
 
-// ----------------------------------------------------------------------------
-// x pass, real -> half (forward).  Tile (y, z chunk); z pairs (2p, 2p+1) ride
-// as the real and imaginary parts of one complex line.
-// ----------------------------------------------------------------------------
+// x pass, real -> half (forward).  Tile (y, z chunk); the z pairs (2p, 2p+1)
+// ride as the real and imaginary parts of one complex line of length N.
+template <typename R, int N> struct XCfg {
+    static constexpr int TZ = Shape<R, N>::TZ;
+    static constexpr int P = TZ / 2;
+    static constexpr int NT = CMin<256, CMax<64, P * TPConst<N>::RMAX>::v>::v;
+};
+
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_xpass_r2c(const R* __restrict__ in, typename CplxOf<R>::T* __restrict__ out,
                                                    const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
-    constexpr int TZ = Shape<R, N>::TZ;
-    constexpr int P = TZ / 2;
+    constexpr int TZ = XCfg<R, N>::TZ;
+    constexpr int P = XCfg<R, N>::P;
+    constexpr int NT = XCfg<R, N>::NT;
     constexpr int NZC = N / TZ;
     constexpr int H = N / 2 + 1;
     constexpr int LS = N + 1;
-    constexpr int NT = 256;
-    __shared__ C buf[P * LS];
+    __shared__ C lds[TPLayout<N, P, true>::size];
+    __shared__ C zb[P * LS];
     const int tid = threadIdx.x;
     const int zc = blockIdx.x % NZC;
     const int y = blockIdx.x / NZC;
     const int z0 = zc * TZ;
     const C* inc = reinterpret_cast<const C*>(in);
-    for (int e = tid; e < N * P; e += NT) {
-        const int x = e / P, p = e % P;
-        buf[p * LS + x] = inc[((long(x) * N + y) * N + z0) / 2 + p];
-    }
+    auto ld = [&](int p, int x) -> C { return inc[((long(x) * N + y) * N + z0) / 2 + p]; };
+    auto st = [&](int p, int k, C v) { zb[p * LS + k] = v; };
+    tp_phase1<C, N, -1, P, NT, true>(ld, lds, tw, tid);
     __syncthreads();
-    lds_fft<C, N, P, NT, -1, LS, 1>(buf, tw, tid);
+    tp_phase2<C, N, -1, P, NT, true>(st, lds, tw, tid);
+    __syncthreads();
     for (int e = tid; e < H * P; e += NT) {
         const int k = e / P, p = e % P;
-        const C zk = buf[p * LS + k];
-        const C zm = buf[p * LS + ((N - k) % N)];
+        const C zk = zb[p * LS + k];
+        const C zm = zb[p * LS + ((N - k) % N)];
         const C a = cmk<C>(R(0.5) * (zk.x + zm.x), R(0.5) * (zk.y - zm.y));
         const C bb = cmk<C>(R(0.5) * (zk.y + zm.y), R(-0.5) * (zk.x - zm.x));
         C* o = out + (long(k) * N + y) * N + z0 + 2 * p;
@@ -271,42 +300,44 @@ __global__ __launch_bounds__(256) void k_xpass_r2c(const R* __restrict__ in, typ
     }
 }
 
-// ----------------------------------------------------------------------------
+// Hermitian-extended pair line for the inverse along x: element n of line p
+// is X_a[n] + i X_b[n] (n <= N/2) or conj(X_a[N-n]) + i conj(X_b[N-n]), with
+// X_a, X_b the z = 2p and 2p+1 columns of the half spectrum at (y, z0);
+// the imaginary parts at kx = 0 and N/2 are dropped (real-input convention).
+template <typename C, int N>
+__device__ __forceinline__ C herm_pair(const C* __restrict__ col, int n) {
+    using R = decltype(C::x);
+    const int k = n <= N / 2 ? n : N - n;
+    const C* src = col + long(k) * N * N;
+    C a = src[0], b = src[1];
+    if (k == 0 || k == N / 2) {
+        a.y = R(0);
+        b.y = R(0);
+    }
+    return n <= N / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
+}
+
 // x pass, half -> real (inverse).
-// ----------------------------------------------------------------------------
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_xpass_c2r(const typename CplxOf<R>::T* __restrict__ in, R* __restrict__ out,
                                                    const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
-    constexpr int TZ = Shape<R, N>::TZ;
-    constexpr int P = TZ / 2;
+    constexpr int TZ = XCfg<R, N>::TZ;
+    constexpr int P = XCfg<R, N>::P;
+    constexpr int NT = XCfg<R, N>::NT;
     constexpr int NZC = N / TZ;
-    constexpr int H = N / 2 + 1;
-    constexpr int LS = N + 1;
-    constexpr int NT = 256;
-    __shared__ C buf[P * LS];
+    __shared__ C lds[TPLayout<N, P, true>::size];
     const int tid = threadIdx.x;
     const int zc = blockIdx.x % NZC;
     const int y = blockIdx.x / NZC;
     const int z0 = zc * TZ;
-    for (int e = tid; e < H * P; e += NT) {
-        const int k = e / P, p = e % P;
-        const C* src = in + (long(k) * N + y) * N + z0 + 2 * p;
-        C a = src[0], b = src[1];
-        if (k == 0 || k == N / 2) {
-            a.y = R(0);
-            b.y = R(0);
-        }
-        buf[p * LS + k] = cmk<C>(a.x - b.y, a.y + b.x);
-        if (k > 0 && k < N / 2) buf[p * LS + (N - k)] = cmk<C>(a.x + b.y, b.x - a.y);
-    }
-    __syncthreads();
-    lds_fft<C, N, P, NT, +1, LS, 1>(buf, tw, tid);
     C* outc = reinterpret_cast<C*>(out);
-    for (int e = tid; e < N * P; e += NT) {
-        const int x = e / P, p = e % P;
-        outc[((long(x) * N + y) * N + z0) / 2 + p] = buf[p * LS + x];
-    }
+    const C* col0 = in + long(y) * N + z0;
+    auto ld = [&](int p, int n) -> C { return herm_pair<C, N>(col0 + 2 * p, n); };
+    auto st = [&](int p, int x, C v) { outc[((long(x) * N + y) * N + z0) / 2 + p] = v; };
+    tp_phase1<C, N, +1, P, NT, true>(ld, lds, tw, tid);
+    __syncthreads();
+    tp_phase2<C, N, +1, P, NT, true>(st, lds, tw, tid);
 }
 
 // ----------------------------------------------------------------------------
@@ -409,9 +440,19 @@ __global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_tar
 
 // ----------------------------------------------------------------------------
 // gen_z: Fourier weighting fused into the first inverse pass (along z).
-// Block = RBG rows (kx, ky).  For each kept term a: V = phi_a(u) Phi_hat / V,
-// fields i qt_j V (j = x, y, z), inverse DFT along z, stored to T.
+// Block = RB rows (kx, ky).  Phase-1 items are (row, t); each holds the R1
+// elements kz = t + R2 m of its row (Phi_hat / V, u-interval, gradient
+// wavevector) in registers for the whole loop over kept terms a, forms the
+// three fields i qt_j phi_a(u) Phi_hat / V and runs their first register DFT.
 // ----------------------------------------------------------------------------
+template <typename R, int N> struct GCfg {
+    static constexpr int R1 = TPConst<N>::R1;
+    static constexpr int R2 = TPConst<N>::R2;
+    static constexpr int RB0 = (sizeof(R) == 4 ? 2048 : 1024) / N;
+    static constexpr int RB = pow2_floor(CMin<CMax<1, RB0>::v, N>::v);
+    static constexpr int NT = CMin<256, CMax<64, RB * R2>::v>::v;
+};
+
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __restrict__ phi_hat,
                                                const int16_t* __restrict__ lut_u, const R* __restrict__ phi_tab,
@@ -419,58 +460,80 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
                                                typename CplxOf<R>::T* __restrict__ T,
                                                const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
-    constexpr int RB = Shape<R, N>::RBG_;
+    using G = GCfg<R, N>;
+    constexpr int RB = G::RB, NT = G::NT, R1 = G::R1, R2 = G::R2;
+    constexpr int NL = 3 * RB;
+    using Lay = TPLayout<N, NL, false>;
     constexpr long FS = Shape<R, N>::FS;
-    constexpr int NT = 256;
-    constexpr int E = (RB * N + NT - 1) / NT;
-    constexpr int LS = N;
-    __shared__ C buf[3 * RB * LS];
+    constexpr int ITEMS = RB * R2;
+    constexpr int PER = (ITEMS + NT - 1) / NT;
+    __shared__ C lds[Lay::size];
     const int tid = threadIdx.x;
     const long row0 = long(blockIdx.x) * RB;
-    C ph[E];
-    int idx[E];
-    R q[E][3];
+    C ph[PER][R1];
+    int16_t idx[PER][R1];
+    R qxy[PER][2];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int e = tid + i * NT;
-        idx[i] = -1;
-        ph[i] = cmk<C>(R(0), R(0));
-        q[i][0] = q[i][1] = q[i][2] = R(0);
-        if (e < RB * N) {
-            const long r = row0 + e / N;
-            const int kz = e % N;
-            const int kx = int(r / N), ky = int(r % N);
-            const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
-            ph[i] = phi_hat[r * N + kz];
-            ph[i] = cmk<C>(ph[i].x * inv_V, ph[i].y * inv_V);
-            idx[i] = lut_u[nx * nx + ny * ny + nz * nz];
-            q[i][0] = (nx == -N / 2) ? R(0) : k_F * R(nx);
-            q[i][1] = (ny == -N / 2) ? R(0) : k_F * R(ny);
-            q[i][2] = (nz == -N / 2) ? R(0) : k_F * R(nz);
+    for (int i = 0; i < PER; ++i) {
+        const int w = tid + i * NT;
+        const bool ok = (ITEMS % NT == 0) || w < ITEMS;
+        const int row = ok ? w / R2 : 0, t = ok ? w % R2 : 0;
+        const long r = row0 + row;
+        const int kx = int(r / N), ky = int(r % N);
+        const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+        qxy[i][0] = (nx == -N / 2) ? R(0) : k_F * R(nx);
+        qxy[i][1] = (ny == -N / 2) ? R(0) : k_F * R(ny);
+#pragma unroll
+        for (int m = 0; m < R1; ++m) {
+            const int kz = t + R2 * m;
+            const int nz = signed_index(kz, N);
+            const C v = ok ? phi_hat[r * N + kz] : cmk<C>(R(0), R(0));
+            ph[i][m] = cmk<C>(v.x * inv_V, v.y * inv_V);
+            idx[i][m] = ok ? lut_u[nx * nx + ny * ny + nz * nz] : int16_t(-1);
         }
     }
     for (int a = a0; a < a0 + na; ++a) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int e = tid + i * NT;
-            if (e < RB * N) {
-                const int row = e / N, kz = e % N;
-                const R w = idx[i] >= 0 ? phi_tab[idx[i] * n_alpha + a] : R(0);
-                const C v = cmk<C>(ph[i].x * w, ph[i].y * w);
-                // i q v = (-q v.y, q v.x)
+        for (int i = 0; i < PER; ++i) {
+            const int w = tid + i * NT;
+            if ((ITEMS % NT == 0) || w < ITEMS) {
+                const int row = w / R2, t = w % R2;
+                C v[R1];
 #pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    buf[(j * RB + row) * LS + kz] = cmk<C>(-q[i][j] * v.y, q[i][j] * v.x);
+                for (int m = 0; m < R1; ++m) {
+                    const R wgt = idx[i][m] >= 0 ? phi_tab[idx[i][m] * n_alpha + a] : R(0);
+                    v[m] = cmk<C>(ph[i][m].x * wgt, ph[i][m].y * wgt);
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    C f[R1];
+#pragma unroll
+                    for (int m = 0; m < R1; ++m) {
+                        R q;
+                        if (j < 2) q = qxy[i][j];
+                        else {
+                            const int nz = signed_index(t + R2 * m, N);
+                            q = (nz == -N / 2) ? R(0) : k_F * R(nz);
+                        }
+                        f[m] = cmk<C>(-q * v[m].y, q * v[m].x);   // i q v
+                    }
+                    reg_dft<R1, +1, N>(f, tw);
+#pragma unroll
+                    for (int k1 = 0; k1 < R1; ++k1) {
+                        C o = f[k1];
+                        if (k1 > 0) o = cmul(o, tw_at<+1, N>(tw, t * k1));
+                        lds[Lay::at(j * RB + row, k1, t)] = o;
+                    }
+                }
             }
         }
         __syncthreads();
-        lds_fft<C, N, 3 * RB, NT, +1, LS, 1>(buf, tw, tid);
         const long fbase = long(3 * (a - a0)) * FS;
-        for (int e = tid; e < 3 * RB * N; e += NT) {
-            const int line = e / N, kz = e % N;
+        auto st = [&](int line, int kz, C v) {
             const int j = line / RB, row = line % RB;
-            T[fbase + long(j) * FS + (row0 + row) * N + kz] = buf[line * LS + kz];
-        }
+            T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
+        };
+        tp_phase2<C, N, +1, NL, NT, false>(st, lds, tw, tid);
         __syncthreads();
     }
 }
@@ -495,7 +558,9 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
     constexpr int H = N / 2 + 1;
     constexpr long FS = S::FS;
     constexpr int LS = N + 1;
-    __shared__ C Z[3 * P * LS];
+    constexpr int NLI = 3 * P;                                     // inverse lines
+    constexpr int BUF = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
+    __shared__ C Z[BUF];
     const int tid = threadIdx.x;
     const int zc = blockIdx.x % NZC;
     const int y = blockIdx.x / NZC;
@@ -506,24 +571,20 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
 #pragma unroll
         for (int i = 0; i < PP; ++i) Q[c][i] = cmk<C>(R(0), R(0));
 
+    const C* col0 = T + long(y) * N + z0;
     for (int a = a0; a < a0 + na; ++a) {
-        const long fb = long(3 * (a - a0)) * FS;
-        for (int e = tid; e < 3 * H * P; e += NT) {
-            const int j = e / (H * P);
-            const int rem = e - j * (H * P);
-            const int k = rem / P, p = rem % P;
-            const C* src = T + fb + long(j) * FS + (long(k) * N + y) * N + z0 + 2 * p;
-            C av = src[0], bv = src[1];
-            if (k == 0 || k == N / 2) {
-                av.y = R(0);
-                bv.y = R(0);
-            }
-            C* line = Z + (j * P + p) * LS;
-            line[k] = cmk<C>(av.x - bv.y, av.y + bv.x);
-            if (k > 0 && k < N / 2) line[N - k] = cmk<C>(av.x + bv.y, bv.x - av.y);
-        }
+        const C* colf = col0 + long(3 * (a - a0)) * FS;
+        auto ld = [&](int line, int n) -> C {
+            const int j = line / P, p = line % P;
+            return herm_pair<C, N>(colf + long(j) * FS + 2 * p, n);
+        };
+        tp_phase1<C, N, +1, NLI, NT, true>(ld, Z, tw, tid);
         __syncthreads();
-        lds_fft<C, N, 3 * P, NT, +1, LS, 1>(Z, tw, tid);
+        TPRegs<C, N, +1, NLI, NT, true> g;
+        g.run(Z, tw, tid);
+        __syncthreads();
+        g.store([&](int line, int x, C v) { Z[line * LS + x] = v; }, tid);
+        __syncthreads();
         const R s = sigma[a] * dV;
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
@@ -543,29 +604,32 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
         }
         __syncthreads();
     }
-    // forward DFT along x of the six components, three at a time
+    // forward DFT along x, one component at a time: the P pair lines are
+    // staged at Z[0 .. P*LS) and transposed through Z[P*LS ..)
+    C* zq = Z;
+    C* zt = Z + P * LS;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int c = 0; c < 6; ++c) {
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
             const int qq = tid + i * NT;
-            const int x = qq % N, p = qq / N;
-#pragma unroll
-            for (int cl = 0; cl < 3; ++cl) Z[(cl * P + p) * LS + x] = Q[3 * h + cl][i];
+            zq[(qq / N) * LS + (qq % N)] = Q[c][i];
         }
         __syncthreads();
-        lds_fft<C, N, 3 * P, NT, -1, LS, 1>(Z, tw, tid);
-        for (int e = tid; e < 3 * H * P; e += NT) {
-            const int cl = e / (H * P);
-            const int rem = e - cl * (H * P);
-            const int k = rem / P, p = rem % P;
+        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, tw, tid);
+        __syncthreads();
+        TPRegs<C, N, -1, P, NT, false> f;
+        f.run(zt, tw, tid);
+        f.store([&](int p, int k, C v) { zq[p * LS + k] = v; }, tid);
+        __syncthreads();
+        for (int e = tid; e < H * P; e += NT) {
+            const int k = e / P, p = e % P;
             if (k < n_planes) {
-                const C* line = Z + (cl * P + p) * LS;
-                const C zk = line[k];
-                const C zm = line[(N - k) % N];
+                const C zk = zq[p * LS + k];
+                const C zm = zq[p * LS + ((N - k) % N)];
                 const C A = cmk<C>(R(0.5) * (zk.x + zm.x), R(0.5) * (zk.y - zm.y));
                 const C B = cmk<C>(R(0.5) * (zk.y + zm.y), R(-0.5) * (zk.x - zm.x));
-                C* o = Qx + long(3 * h + cl) * FS + (long(k) * N + y) * N + z0 + 2 * p;
+                C* o = Qx + long(c) * FS + (long(k) * N + y) * N + z0 + 2 * p;
                 if (accumulate) {
                     const C oa = o[0], ob = o[1];
                     o[0] = cadd(oa, A);
@@ -633,8 +697,10 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
     constexpr int RB = Shape<R, N>::RBB_;
     constexpr long FS = Shape<R, N>::FS;
     constexpr int NT = 256;
+    constexpr int NL = 12 * RB;
     constexpr int LS = N;
-    __shared__ C buf[12 * RB * LS];
+    constexpr int BUF = CMax<TPLayout<N, NL, false>::size, NL * LS>::v;
+    __shared__ C buf[BUF];
     __shared__ double rsum[NT / 64];
     __shared__ unsigned long long rcnt[NT / 64];
     const int tid = threadIdx.x;
@@ -652,13 +718,17 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
     double acc = 0.0;
     unsigned long long cnt = 0ull;
     if (any) {
-        for (int e = tid; e < 12 * RB * N; e += NT) {
-            const int line = e / N, kz = e % N;
+        auto ld = [&](int line, int kz) -> C {
             const int comp = line / RB, row = line % RB;
-            buf[line * LS + kz] = Qxy[long(comp) * FS + (row0 + row) * N + kz];
-        }
+            return Qxy[long(comp) * FS + (row0 + row) * N + kz];
+        };
+        tp_phase1<C, N, -1, NL, NT, false>(ld, buf, tw, tid);
         __syncthreads();
-        lds_fft<C, N, 12 * RB, NT, -1, LS, 1>(buf, tw, tid);
+        TPRegs<C, N, -1, NL, NT, false> f;
+        f.run(buf, tw, tid);
+        __syncthreads();
+        f.store([&](int line, int kz, C v) { buf[line * LS + kz] = v; }, tid);
+        __syncthreads();
         for (int e = tid; e < RB * N; e += NT) {
             const int row = e / N, kz = e % N;
             const long rr = row0 + row;
@@ -757,23 +827,23 @@ template <typename R, int NN> struct EngineImpl final : Engine {
         k_noise<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(static_cast<R*>(out), total, seed);
     }
     void xpass_r2c(const void* in, void* out, hipStream_t s) override {
-        k_xpass_r2c<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(256), 0, s>>>(static_cast<const R*>(in),
+        k_xpass_r2c<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(XCfg<R, NN>::NT), 0, s>>>(static_cast<const R*>(in),
                                                                       static_cast<C*>(out), tw);
     }
     void xpass_c2r(const void* in, void* out, hipStream_t s) override {
-        k_xpass_c2r<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(256), 0, s>>>(static_cast<const C*>(in),
+        k_xpass_c2r<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(XCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(in),
                                                                       static_cast<R*>(out), tw);
     }
     void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign, hipStream_t s) override {
         const unsigned blocks = unsigned(long(n_fields) * n_planes * (NN / S::TZ));
         if (blocks == 0) return;
         if (sign < 0)
-            k_ypass<R, NN, -1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+            k_ypass<R, NN, -1><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
         else
-            k_ypass<R, NN, +1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+            k_ypass<R, NN, +1><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
     }
     void zpass(void* data, long n_rows, int sign, hipStream_t s) override {
-        const unsigned blocks = unsigned((n_rows + S::RBZ_ - 1) / S::RBZ_);
+        const unsigned blocks = unsigned((n_rows + ZCfg<R, NN>::RB - 1) / ZCfg<R, NN>::RB);
         if (blocks == 0) return;
         if (sign < 0)
             k_zpass<R, NN, -1><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<C*>(data), n_rows, tw);
@@ -802,8 +872,8 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     }
     void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab, int n_alpha, int a0, int na,
                double k_F, double inv_V, void* T, hipStream_t s) override {
-        const unsigned blocks = unsigned((long(S::H) * NN) / S::RBG_);
-        k_gen_z<R, NN><<<dim3(blocks), dim3(256), 0, s>>>(static_cast<const C*>(phi_hat), lut_u,
+        const unsigned blocks = unsigned((long(S::H) * NN) / GCfg<R, NN>::RB);
+        k_gen_z<R, NN><<<dim3(blocks), dim3(GCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(phi_hat), lut_u,
                                                         static_cast<const R*>(phi_tab), n_alpha, a0, na,
                                                         R(k_F), R(inv_V), static_cast<C*>(T), tw);
     }
