@@ -70,7 +70,11 @@ typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2 } si
  * plan holds, >= 1.  alpha_chunk bounds how many separable terms share one
  * workspace pass (0 = all n_alpha; a smaller value trades a few extra
  * read-modify-write passes for 3*alpha_chunk instead of 3*n_alpha fields of
- * workspace). */
+ * workspace).  scratch_terms is how many terms the first inverse pass
+ * stages at a time (2 half spectra each) before they are expanded into
+ * their gradient fields; 0 picks the largest count (up to alpha_chunk) whose
+ * staging fits in 16 GiB.  A small count keeps the staging resident in the
+ * last-level cache at the price of re-reading Phi_hat per group. */
 typedef struct {
     int32_t N;
     double  L;
@@ -80,6 +84,7 @@ typedef struct {
     int32_t n_alpha;
     double  u_min, u_max, u_p, sigma_p, A_p;
     int32_t alpha_chunk;
+    int32_t scratch_terms;
 } sigw_plan_desc;
 
 /* Log-normal peak, Eq. lognormal: Delta^2(k) = A/sqrt(2 pi sigma^2) exp(-ln^2(k/k_star)/(2 sigma^2)).
@@ -94,7 +99,8 @@ typedef struct { double A, sigma, k_star; } sigw_lognormal;
 typedef struct { int32_t kind; double F_NL, G_NL, beta, clip; } sigw_ngmap;
 
 /* Fill d with the paper's default decomposition (n_modes 200, n_alpha 50,
- * u in [1e-3, 15), u_p 1, sigma_p 0.5, A_p 10), one slot, all terms per pass. */
+ * u in [1e-3, 15), u_p 1, sigma_p 0.5, A_p 10), one slot, all terms per
+ * pass, automatic staging. */
 sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32_t prec);
 
 /* Device bytes a plan with this description allocates (for admission by HBM
@@ -178,11 +184,11 @@ sigw_status sigw_spectrum_poll(sigw_plan_t plan, double* omega_host, int64_t* nm
 /* Block until the plan stream is idle. */
 sigw_status sigw_synchronize(sigw_plan_t plan);
 
-/* Kernel timing of the last completed sigw_spectrum / sigw_spectrum_batch /
- * sigw_spectrum_enqueue: average duration in milliseconds of the launches of
- * the named kernel ("gen_z", "ypass", "xprod", "zbin"), measured with HIP
- * events on the plan stream when timing is enabled, and the number of
- * launches.  Timing is off by default. */
+/* Kernel timing since timing was last enabled, over completed spectra:
+ * average duration in milliseconds of the launches of the named kernel
+ * ("gen_z", "ypass", "xprod", "ypass_q", "zbin"), measured with HIP events
+ * on the plan stream, and the number of launches.  Timing is off by
+ * default; enabling it resets the totals. */
 sigw_status sigw_set_timing(sigw_plan_t plan, int32_t enabled);
 sigw_status sigw_kernel_time(sigw_plan_t plan, const char* name, double* avg_ms, int64_t* launches);
 

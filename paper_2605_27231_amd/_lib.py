@@ -40,6 +40,7 @@ class PlanDesc(ct.Structure):
         ("n_modes", ct.c_int32), ("n_alpha", ct.c_int32),
         ("u_min", ct.c_double), ("u_max", ct.c_double), ("u_p", ct.c_double),
         ("sigma_p", ct.c_double), ("A_p", ct.c_double), ("alpha_chunk", ct.c_int32),
+        ("scratch_terms", ct.c_int32),
     ]
 
 

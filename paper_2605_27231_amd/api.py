@@ -32,12 +32,13 @@ def _i64ptr(a: np.ndarray):
 def plan_desc(N: int, L: float = 2 * math.pi, prec: str = "f32", n_slots: int = 1,
               n_modes: int = 200, n_alpha: int = 50, u_min: float = 1e-3, u_max: float = 15.0,
               u_p: float = 1.0, sigma_p: float = 0.5, A_p: float = 10.0,
-              alpha_chunk: int = 0) -> _lib.PlanDesc:
+              alpha_chunk: int = 0, scratch_terms: int = 0) -> _lib.PlanDesc:
     d = _lib.PlanDesc()
     d.N, d.L, d.prec, d.n_slots = N, L, _prec_code(prec), n_slots
     d.n_modes, d.n_alpha = n_modes, n_alpha
     d.u_min, d.u_max, d.u_p, d.sigma_p, d.A_p = u_min, u_max, u_p, sigma_p, A_p
     d.alpha_chunk = alpha_chunk
+    d.scratch_terms = scratch_terms
     return d
 
 

@@ -48,15 +48,19 @@ struct Engine {
     // k_lo <= k_F sqrt(n2) < k_hi, n2 > 0.
     virtual void lut(double k_F, double k_target, double k_lo, double k_hi, const double* edges,
                      int n_modes, int16_t* lut_u, uint8_t* lut_shell, hipStream_t s) = 0;
-    // Fused weighting + inverse DFT along z: for a = a0..a0+na-1 and j = x, y, z,
-    // T[3(a-a0)+j] = IDFT_z( i qt_j phi_a(u) Phi_hat / V ).
+    // Fused weighting + inverse DFT along z: for a = a0..a0+na-1,
+    // S[2(a-a0)] = IDFT_z( phi_a(u) Phi_hat / V ), S[2(a-a0)+1] = IDFT_z( i qt_z phi_a(u) Phi_hat / V ).
     virtual void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab,
-                       int n_alpha, int a0, int na, double k_F, double inv_V, void* T,
+                       int n_alpha, int a0, int na, double k_F, double inv_V, void* S,
                        hipStream_t s) = 0;
-    // Fused inverse DFT along x + products + forward DFT along x:
+    // Inverse DFT along y of na terms' (W, Z) pairs into their three gradient
+    // fields T[3a + j]: IDFT_y(W), IDFT_y(i qt_y W), IDFT_y(Z).
+    virtual void ypass3(const void* S, int na, void* T, double k_F, hipStream_t s) = 0;
+    // Fused inverse DFT along x (with i qt_x on the first field of each term)
+    // + products + forward DFT along x:
     // Qx_c = DFT_x( sum_a sigma_a dV G_a,i G_a,j ) for the 6 components, on
     // the kx planes [0, n_planes); accumulate adds into Qx instead of storing.
-    virtual void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV,
+    virtual void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, double k_F,
                        void* Qx, int n_planes, int accumulate, hipStream_t s) = 0;
     // Fused forward DFT along z of the 12 components (both kernels) + TT
     // projection + shell sums: one (sum, count) partial per block.

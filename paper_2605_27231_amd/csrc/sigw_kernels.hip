@@ -31,12 +31,12 @@ template <typename R, int N> struct Shape {
     // y-pass / x-pass chunk of contiguous z values (128-byte runs of complex)
     static constexpr int TZ = (sizeof(R) == 4 ? 16 : 8) < N ? (sizeof(R) == 4 ? 16 : 8) : N;
     // xprod chunk: keeps the LDS tile near 50 KB
-    static constexpr int TZX0 = (N >= 384) ? (sizeof(R) == 4 ? 8 : 4) : (sizeof(R) == 4 ? 16 : 8);
+    static constexpr int TZX0 = (N >= 384) ? (sizeof(R) == 4 ? 8 : 4) : (sizeof(R) == 4 ? 8 : 4);
     static constexpr int TZX = TZX0 < N ? TZX0 : N;
     static constexpr int PX = TZX / 2;                    // z pairs per xprod tile
     // threads per xprod block: a divisor of the N * PX point pairs, at most 512
     static constexpr int NPP = N * PX;
-    static constexpr int NTX = NPP <= 512 ? NPP : (NPP % 512 == 0 ? 512 : (NPP % 384 == 0 ? 384 : 256));
+    static constexpr int NTX = NPP <= 256 ? NPP : (NPP % 256 == 0 ? 256 : (NPP % 192 == 0 ? 192 : 128));
     static constexpr int PPX = NPP / NTX;                 // point pairs per thread
     static_assert(NTX * PPX == NPP, "xprod threads must tile the point pairs");
     // z-pass rows per block
@@ -304,16 +304,22 @@ __global__ __launch_bounds__(256) void k_xpass_r2c(const R* __restrict__ in, typ
 // is X_a[n] + i X_b[n] (n <= N/2) or conj(X_a[N-n]) + i conj(X_b[N-n]), with
 // X_a, X_b the z = 2p and 2p+1 columns of the half spectrum at (y, z0);
 // the imaginary parts at kx = 0 and N/2 are dropped (real-input convention).
+// With grad set, both columns are first multiplied by i qt_x(kx),
+// qt_x = k_F n_x (zero at kx = 0 and on the Nyquist plane).  Branch free, so
+// lines with and without the gradient can share a wavefront.
 template <typename C, int N>
-__device__ __forceinline__ C herm_pair(const C* __restrict__ col, int n) {
+__device__ __forceinline__ C herm_pair(const C* __restrict__ col, int n, bool grad = false,
+                                       decltype(C::x) k_F = 0) {
     using R = decltype(C::x);
     const int k = n <= N / 2 ? n : N - n;
     const C* src = col + long(k) * N * N;
     C a = src[0], b = src[1];
-    if (k == 0 || k == N / 2) {
-        a.y = R(0);
-        b.y = R(0);
-    }
+    const bool edge = (k == 0 || k == N / 2);
+    const R q = (grad && !edge) ? k_F * R(k) : R(0);   // i q multiplier on the gradient line
+    const R keep = grad ? R(0) : R(1);
+    const R ky = edge ? R(0) : keep;                    // imaginary parts kept off the edges
+    a = cmk<C>(keep * a.x - q * a.y, ky * a.y + q * a.x);
+    b = cmk<C>(keep * b.x - q * b.y, ky * b.y + q * b.x);
     return n <= N / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
 }
 
@@ -441,9 +447,11 @@ __global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_tar
 // ----------------------------------------------------------------------------
 // gen_z: Fourier weighting fused into the first inverse pass (along z).
 // Block = RB rows (kx, ky).  Phase-1 items are (row, t); each holds the R1
-// elements kz = t + R2 m of its row (Phi_hat / V, u-interval, gradient
-// wavevector) in registers for the whole loop over kept terms a, forms the
-// three fields i qt_j phi_a(u) Phi_hat / V and runs their first register DFT.
+// elements kz = t + R2 m of its row (Phi_hat / V and the u-interval) in
+// registers for the whole loop over kept terms a, and forms two fields:
+//   W_a = IDFT_z( phi_a(u) Phi_hat / V ),  Z_a = IDFT_z( i qt_z phi_a(u) Phi_hat / V ).
+// The x and y gradients are applied later (i qt_y before the y transform,
+// i qt_x in the x pass), so two fields per term cross HBM here, not three.
 // ----------------------------------------------------------------------------
 template <typename R, int N> struct GCfg {
     static constexpr int R1 = TPConst<N>::R1;
@@ -462,7 +470,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
     using C = typename CplxOf<R>::T;
     using G = GCfg<R, N>;
     constexpr int RB = G::RB, NT = G::NT, R1 = G::R1, R2 = G::R2;
-    constexpr int NL = 3 * RB;
+    constexpr int NL = 2 * RB;
     using Lay = TPLayout<N, NL, false>;
     constexpr long FS = Shape<R, N>::FS;
     constexpr int ITEMS = RB * R2;
@@ -472,7 +480,6 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
     const long row0 = long(blockIdx.x) * RB;
     C ph[PER][R1];
     int16_t idx[PER][R1];
-    R qxy[PER][2];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int w = tid + i * NT;
@@ -481,8 +488,6 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
         const long r = row0 + row;
         const int kx = int(r / N), ky = int(r % N);
         const int nx = signed_index(kx, N), ny = signed_index(ky, N);
-        qxy[i][0] = (nx == -N / 2) ? R(0) : k_F * R(nx);
-        qxy[i][1] = (ny == -N / 2) ? R(0) : k_F * R(ny);
 #pragma unroll
         for (int m = 0; m < R1; ++m) {
             const int kz = t + R2 * m;
@@ -505,17 +510,17 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
                     v[m] = cmk<C>(ph[i][m].x * wgt, ph[i][m].y * wgt);
                 }
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
+                for (int j = 0; j < 2; ++j) {
                     C f[R1];
 #pragma unroll
                     for (int m = 0; m < R1; ++m) {
-                        R q;
-                        if (j < 2) q = qxy[i][j];
-                        else {
+                        if (j == 0) {
+                            f[m] = v[m];
+                        } else {
                             const int nz = signed_index(t + R2 * m, N);
-                            q = (nz == -N / 2) ? R(0) : k_F * R(nz);
+                            const R q = (nz == -N / 2) ? R(0) : k_F * R(nz);
+                            f[m] = cmk<C>(-q * v[m].y, q * v[m].x);   // i q_z v
                         }
-                        f[m] = cmk<C>(-q * v[m].y, q * v[m].x);   // i q v
                     }
                     reg_dft<R1, +1, N>(f, tw);
 #pragma unroll
@@ -528,7 +533,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
             }
         }
         __syncthreads();
-        const long fbase = long(3 * (a - a0)) * FS;
+        const long fbase = long(2 * (a - a0)) * FS;
         auto st = [&](int line, int kz, C v) {
             const int j = line / RB, row = line % RB;
             T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
@@ -539,13 +544,69 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
 }
 
 // ----------------------------------------------------------------------------
+// ypass3: inverse DFT along y that expands the two z-transformed fields of
+// each term into its three gradient fields:
+//   U_x = IDFT_y(W_a),  U_y = IDFT_y(i qt_y W_a),  U_z = IDFT_y(Z_a)
+// (U_x still lacks its factor i qt_x, applied by the x pass).  Tile (term,
+// kx plane, z chunk); the three outputs are transformed one after another
+// through the same LDS tile.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __restrict__ S,
+                                                typename CplxOf<R>::T* __restrict__ T, R k_F,
+                                                const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int TZ = YCfg<R, N>::TZ;
+    constexpr int NT = YCfg<R, N>::NT;
+    constexpr int NZC = N / TZ;
+    constexpr int H = N / 2 + 1;
+    constexpr long FS = Shape<R, N>::FS;
+    __shared__ C lds[TPLayout<N, TZ, true>::size];
+    const int tid = threadIdx.x;
+    const long b = blockIdx.x;
+    const int zc = int(b % NZC);
+    const long fp = b / NZC;
+    const int kx = int(fp % H);
+    const long al = fp / H;
+    const long off = long(kx) * N * N + zc * TZ;
+    const C* w = S + 2 * al * FS + off;
+    const C* z = w + FS;
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+        const C* src = j == 2 ? z : w;
+        C* dst = T + (3 * al + j) * FS + off;
+        auto ld = [&](int zz, int y) -> C {
+            C v = src[long(y) * N + zz];
+            if (j == 1) {
+                const int ny = signed_index(y, N);
+                const R q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+                v = cmk<C>(-q * v.y, q * v.x);
+            }
+            return v;
+        };
+        auto st = [&](int zz, int y, C v) { dst[long(y) * N + zz] = v; };
+        tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, tw, tid);
+        __syncthreads();
+        tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tw, tid);
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
 // xprod: last inverse pass (x, complex -> real) + products + first forward
 // pass (x, real -> complex).  Block = (y, z chunk of TZX).  Q stays in
 // registers across all kept terms.
+//
+// Per term the raw tile (3 fields x (N/2+1) kx x TZX z values) is loaded
+// once, coalesced, straight from global memory into LDS by the gfx950
+// global-to-LDS loads (no registers involved), double buffered: the tile of
+// term a+1 is in flight while term a is transformed and multiplied.  The
+// Hermitian extension of the x lines (and the factor i qt_x of the first
+// field) is applied when phase 1 reads the tile back.
 // ----------------------------------------------------------------------------
 template <typename R, int N>
-__global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __restrict__ T, const R* __restrict__ sigma,
-                                               int a0, int na, R dV, typename CplxOf<R>::T* __restrict__ Qx,
+__global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* __restrict__ T, const R* __restrict__ sigma,
+                                               int a0, int na, R dV, R k_F, typename CplxOf<R>::T* __restrict__ Qx,
                                                int n_planes, int accumulate,
                                                const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
@@ -558,9 +619,11 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
     constexpr int H = N / 2 + 1;
     constexpr long FS = S::FS;
     constexpr int LS = N + 1;
-    constexpr int NLI = 3 * P;                                     // inverse lines
-    constexpr int BUF = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
-    __shared__ C Z[BUF];
+    constexpr int NLI = 3 * P;                                   // inverse lines (field, z pair)
+    constexpr int NRAW = 3 * H * P;                              // raw pairs per term
+    constexpr int TRS = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
+    __shared__ C raw[2][2 * NRAW];                               // [buffer][field][kx][pair][2]
+    __shared__ C Z[TRS];                                         // transpose, then G lines
     const int tid = threadIdx.x;
     const int zc = blockIdx.x % NZC;
     const int y = blockIdx.x / NZC;
@@ -572,12 +635,53 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
         for (int i = 0; i < PP; ++i) Q[c][i] = cmk<C>(R(0), R(0));
 
     const C* col0 = T + long(y) * N + z0;
+    // 16-byte units: a raw element (two complex) is 1 unit in FP32, 2 in FP64
+    constexpr int UPE = int(2 * sizeof(C) / 16);
+    constexpr int NU = NRAW * UPE;
+    static_assert(NT % 64 == 0 || NT < 64, "global-to-LDS loads are issued per whole wavefront");
+    auto issue_tile = [&](int a, C* dst) {
+        const char* colf = reinterpret_cast<const char*>(col0 + long(3 * (a - a0)) * FS);
+        char* dstb = reinterpret_cast<char*>(dst);
+        const int lane = tid & 63;
+        for (int u0 = tid - lane; u0 < NU; u0 += NT) {       // u0 is uniform in the wavefront
+            const int u = u0 + lane;
+            if (u < NU) {
+                const int e = u / UPE, h = u - e * UPE;
+                const int j = e / (H * P);
+                const int rem = e - j * (H * P);
+                const int k = rem / P, p = rem - k * P;
+                const char* src = colf + (long(j) * FS + long(k) * N * N + 2 * p) * long(sizeof(C)) + 16 * h;
+                // lane i of the wavefront lands at dstb + 16 (u0 + i)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                                 (__attribute__((address_space(3))) void*)(dstb + 16L * u0), 16, 0,
+                                                 0);
+            }
+        }
+    };
+    const C* rawc = raw[0];
+    // element n of inverse line (j, p), from the raw tile
+    auto ld = [&](int line, int n) -> C {
+        const int j = line / P, p = line % P;
+        const int k = n <= N / 2 ? n : N - n;
+        const int e = (j * H + k) * P + p;
+        C a = rawc[2 * e], b = rawc[2 * e + 1];
+        const bool edge = (k == 0 || k == N / 2);
+        const bool grad = (j == 0);
+        const R q = (grad && !edge) ? k_F * R(k) : R(0);
+        const R keep = grad ? R(0) : R(1);
+        const R ky = edge ? R(0) : keep;
+        a = cmk<C>(keep * a.x - q * a.y, ky * a.y + q * a.x);
+        b = cmk<C>(keep * b.x - q * b.y, ky * b.y + q * b.x);
+        return n <= N / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
+    };
+
+    issue_tile(a0, raw[0]);
     for (int a = a0; a < a0 + na; ++a) {
-        const C* colf = col0 + long(3 * (a - a0)) * FS;
-        auto ld = [&](int line, int n) -> C {
-            const int j = line / P, p = line % P;
-            return herm_pair<C, N>(colf + long(j) * FS + 2 * p, n);
-        };
+        const int cur = (a - a0) & 1;
+        __builtin_amdgcn_s_waitcnt(0);    // this wavefront's loads of tile a have landed
+        __syncthreads();                  // ... and every wavefront's; Z is free again
+        if (a + 1 < a0 + na) issue_tile(a + 1, raw[cur ^ 1]);
+        rawc = raw[cur];
         tp_phase1<C, N, +1, NLI, NT, true>(ld, Z, tw, tid);
         __syncthreads();
         TPRegs<C, N, +1, NLI, NT, true> g;
@@ -602,8 +706,10 @@ __global__ __launch_bounds__(512) void k_xprod(const typename CplxOf<R>::T* __re
             Q[4][i] = cmk<C>(Q[4][i].x + sx.x * gz.x, Q[4][i].y + sx.y * gz.y);
             Q[5][i] = cmk<C>(Q[5][i].x + sy.x * gz.x, Q[5][i].y + sy.y * gz.y);
         }
-        __syncthreads();
+        // tile a+2 goes into raw[cur] only after the next barrier, when
+        // phase 1 of this term has long finished reading it
     }
+    __syncthreads();
     // forward DFT along x, one component at a time: the P pair lines are
     // staged at Z[0 .. P*LS) and transposed through Z[P*LS ..)
     C* zq = Z;
@@ -877,12 +983,18 @@ template <typename R, int NN> struct EngineImpl final : Engine {
                                                         static_cast<const R*>(phi_tab), n_alpha, a0, na,
                                                         R(k_F), R(inv_V), static_cast<C*>(T), tw);
     }
-    void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, void* Qx, int n_planes,
-               int accumulate, hipStream_t s) override {
+    void ypass3(const void* Sd, int na, void* T, double k_F, hipStream_t s) override {
+        const unsigned blocks = unsigned(long(na) * S::H * (NN / YCfg<R, NN>::TZ));
+        if (blocks == 0) return;
+        k_ypass3<R, NN><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(Sd),
+                                                                      static_cast<C*>(T), R(k_F), tw);
+    }
+    void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, double k_F, void* Qx,
+               int n_planes, int accumulate, hipStream_t s) override {
         const unsigned blocks = unsigned(NN * (NN / S::TZX));
         k_xprod<R, NN><<<dim3(blocks), dim3(S::NTX), 0, s>>>(static_cast<const C*>(T),
                                                            static_cast<const R*>(sigma_tab), a0, na, R(dV),
-                                                           static_cast<C*>(Qx), n_planes, accumulate, tw);
+                                                           R(k_F), static_cast<C*>(Qx), n_planes, accumulate, tw);
     }
     void zbin(const void* Qxy, const uint8_t* lut_shell, int n2_lo, int n2_hi, double* ps,
               unsigned long long* pc, hipStream_t s) override {

@@ -171,14 +171,21 @@ const char* validate(const sigw_plan_desc* d) {
         return "need 0 < u_min < u_max";
     if (!(d->sigma_p > 0.0) || !(d->A_p >= 0.0) || !std::isfinite(d->u_p)) return "need sigma_p > 0, A_p >= 0";
     if (d->alpha_chunk < 0 || d->alpha_chunk > d->n_alpha) return "alpha_chunk must be in [0, n_alpha]";
+    if (d->scratch_terms < 0 || d->scratch_terms > d->n_alpha) return "scratch_terms must be in [0, n_alpha]";
     return nullptr;
 }
 
 struct Sizes {
     long H, FS, R3, n2max;
     size_t cb, rb;
-    int chunk;
+    int chunk;     // terms per xprod pass (workspace T holds 3 * chunk fields)
+    int stage;     // terms staged per gen_z / ypass3 pair (scratch holds 2 * stage fields)
 };
+
+// Default staging: every term of a pass at once when the (W, Z) pairs fit in
+// 16 GiB (Phi_hat is then read once per kernel and target), else as many
+// terms as fit.
+constexpr size_t kStageBudget = size_t(16) << 30;
 
 Sizes sizes_of(const sigw_plan_desc& d) {
     Sizes z;
@@ -189,6 +196,12 @@ Sizes sizes_of(const sigw_plan_desc& d) {
     z.rb = d.prec == SIGW_F64 ? 8 : 4;
     z.cb = 2 * z.rb;
     z.chunk = d.alpha_chunk == 0 ? d.n_alpha : d.alpha_chunk;
+    if (d.scratch_terms > 0) {
+        z.stage = std::min(d.scratch_terms, z.chunk);
+    } else {
+        const size_t per = size_t(2) * z.FS * z.cb;
+        z.stage = int(std::max<size_t>(1, std::min<size_t>(kStageBudget / per, size_t(z.chunk))));
+    }
     return z;
 }
 
@@ -205,6 +218,7 @@ size_t footprint_of(const sigw_plan_desc& d) {
     b += size_t(z.n2max + 1) * (2 + 1 + 8);                    // lut_u, lut_shell, amp
     b += size_t(d.n_slots) * z.FS * z.cb;                      // Phi_hat per slot
     b += size_t(3) * z.chunk * z.FS * z.cb;                    // gradient-field workspace
+    b += size_t(2) * z.stage * z.FS * z.cb;                    // staged (W, Z) pairs
     b += size_t(12) * z.FS * z.cb;                             // Q components (both kernels)
     b += size_t(z.R3) * z.rb;                                  // real scratch
     b += size_t(zb) * 16 + size_t(kSumsqBlocks + 1) * 8;       // partials
@@ -236,6 +250,7 @@ struct sigw_plan {
     double* amp = nullptr;
     void* phi_hat = nullptr;
     void* T = nullptr;
+    void* Sst = nullptr;
     void* Q = nullptr;
     void* real = nullptr;
     double* part_sum = nullptr;
@@ -358,14 +373,20 @@ sigw_status enqueue_convolutions(sigw_plan* p, int slot, double k_target, int n_
         for (int a0 = 0; a0 < d.n_alpha; a0 += z.chunk) {
             const int na = std::min(z.chunk, d.n_alpha - a0);
             sigw_status s;
-            s = timed(p, 0, [&] {
-                p->eng->gen_z(ph, p->lut_u, p->phi_tab[m], d.n_alpha, a0, na, kF, 1.0 / V, p->T, p->stream);
-            });
-            if (s) return s;
-            s = timed(p, 1, [&] { p->eng->ypass(p->T, 3 * na, z.FS, int(z.H), +1, p->stream); });
-            if (s) return s;
+            // stage a few terms at a time: (W, Z) pairs small enough to stay in
+            // the last-level cache between gen_z and ypass3
+            for (int as = a0; as < a0 + na; as += z.stage) {
+                const int ns = std::min(z.stage, a0 + na - as);
+                void* Tdst = cplx_at(p->T, long(3) * (as - a0) * z.FS, z.cb);
+                s = timed(p, 0, [&] {
+                    p->eng->gen_z(ph, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V, p->Sst, p->stream);
+                });
+                if (s) return s;
+                s = timed(p, 1, [&] { p->eng->ypass3(p->Sst, ns, Tdst, kF, p->stream); });
+                if (s) return s;
+            }
             s = timed(p, 2, [&] {
-                p->eng->xprod(p->T, p->sigma_tab[m], a0, na, dV, Qm, n_planes, a0 > 0 ? 1 : 0, p->stream);
+                p->eng->xprod(p->T, p->sigma_tab[m], a0, na, dV, kF, Qm, n_planes, a0 > 0 ? 1 : 0, p->stream);
             });
             if (s) return s;
         }
@@ -470,6 +491,7 @@ sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32
     d->sigma_p = 0.5;
     d->A_p = 10.0;
     d->alpha_chunk = 0;
+    d->scratch_terms = 0;
     return SIGW_OK;
 }
 
@@ -499,7 +521,7 @@ sigw_status sigw_plan_destroy(sigw_plan_t p) {
     if (!p) return SIGW_E_INVALID;
     (void)hipStreamSynchronize(p->stream);
     void* bufs[] = {p->tw, p->edges, p->phi_tab[0], p->phi_tab[1], p->sigma_tab[0], p->sigma_tab[1],
-                    p->lut_u, p->lut_shell, p->amp, p->phi_hat, p->T, p->Q, p->real, p->part_sum,
+                    p->lut_u, p->lut_shell, p->amp, p->phi_hat, p->T, p->Sst, p->Q, p->real, p->part_sum,
                     p->part_cnt, p->sq_part, p->sums, p->cnts};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -557,7 +579,8 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
               alloc((void**)&P->lut_u, size_t(z.n2max + 1) * 2) && alloc((void**)&P->lut_shell, size_t(z.n2max + 1)) &&
               alloc((void**)&P->amp, size_t(z.n2max + 1) * 8) &&
               alloc(&P->phi_hat, size_t(d->n_slots) * z.FS * z.cb) &&
-              alloc(&P->T, size_t(3) * z.chunk * z.FS * z.cb) && alloc(&P->Q, size_t(12) * z.FS * z.cb) &&
+              alloc(&P->T, size_t(3) * z.chunk * z.FS * z.cb) && alloc(&P->Sst, size_t(2) * z.stage * z.FS * z.cb) &&
+              alloc(&P->Q, size_t(12) * z.FS * z.cb) &&
               alloc(&P->real, size_t(z.R3) * z.rb) && alloc((void**)&P->part_sum, size_t(zb_max) * 8) &&
               alloc((void**)&P->part_cnt, size_t(zb_max) * 8) &&
               alloc((void**)&P->sq_part, size_t(kSumsqBlocks + 1) * 8) &&

@@ -51,7 +51,8 @@ def test_desc_default_and_validation():
     bad = []
     for field, val in (("N", 100), ("N", 0), ("L", -1.0), ("prec", 3), ("n_slots", 0),
                        ("n_alpha", 201), ("n_alpha", 0), ("u_min", 0.0), ("u_max", 1e-4),
-                       ("sigma_p", 0.0), ("alpha_chunk", 51)):
+                       ("sigma_p", 0.0), ("alpha_chunk", 51), ("scratch_terms", -1),
+                       ("scratch_terms", 51)):
         dd = P.plan_desc(64)
         setattr(dd, field, val)
         bad.append(L.sigw_plan_create(ct.byref(dd), None, ct.byref(out)))
@@ -70,7 +71,8 @@ def test_footprint_formula():
     for N, prec, cb in ((64, "f32", 8), (256, "f32", 8), (256, "f64", 16), (512, "f32", 8)):
         d = P.plan_desc(N, prec=prec)
         fs = (N // 2 + 1) * N * N
-        main = (1 + 150 + 12) * fs * cb + N ** 3 * cb // 2
+        stage = max(1, min(50, (16 << 30) // (2 * fs * cb)))
+        main = (1 + 150 + 2 * stage + 12) * fs * cb + N ** 3 * cb // 2
         got = P.sigw_plan_footprint(d)
         assert main <= got <= main * 1.01 + 4e6, (N, prec, got, main)
     # fewer terms per pass shrink the workspace
