@@ -34,6 +34,19 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (scaled by a 1 GiB copy: reads x2.0, writes x1.0), valid only for the
+# kernel source they were taken on; see profiles/hbm_counters_localNG256_fp32.md.
+COUNTER_SOURCE_SHA = "151d0df02fed5aef"
+COUNTER_TRAFFIC = {"xprod": 20367920171.5, "ypass": 19300594466.5, "gen_z": 6840692284.5}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2605_27231_amd", "csrc", "sigw_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def stage_terms(N: int, cb: int, n_alpha: int = 50) -> int:
     """Terms the library stages per gen_z / ypass3 pair with the default plan
@@ -122,7 +135,10 @@ def run_gpu(args):
     res = {
         "value": value, "dt": dt, "n_targets": n_targets, "omega_seed_last": om.tolist(),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": (COUNTER_TRAFFIC.get(dom) if kernel_source_sha() == COUNTER_SOURCE_SHA
+                                 else None),
+                     "kernel": dom,
                      "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(ms_d, 4),
                      "launches": n_d},
         "kernels": kernels,
@@ -144,6 +160,26 @@ def run_gpu(args):
         res["fp64_path"] = {"spectra_per_s": 1.0 / d64, "speedup_fp32_over_fp64": value * d64,
                             "what": "seed 0 only, same bins, FP64 fields/FFTs"}
     return res
+
+
+def quick_profile():
+    """A short run for hardware-counter passes: one 256^3 field, the peak
+    target, and a plain 1 GiB device copy whose counter readings calibrate
+    the byte counters (read 1 GiB, write 1 GiB)."""
+    import torch
+    import paper_2605_27231_amd as P
+
+    job = W.config_local_ng(256, 64)
+    b = int(np.argmin(np.abs(job.targets - job.spectrum.k_star * 2 / math.sqrt(3))))
+    with P.Plan(job.N, L=job.L, prec="f32") as plan:
+        plan.generate_field(0, 0, job.spectrum, job.ngmap)
+        om, nb = plan.spectrum(0, job.targets[b:b + 1], job.k_lo[b:b + 1], job.k_hi[b:b + 1])
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"quick": True, "target": float(job.targets[b]), "omega": float(om[0]),
+                      "nmodes": int(nb[0]), "copy_bytes": 1 << 30}), flush=True)
 
 
 def cpu_baseline(budget_terms=(1, 6)):
@@ -191,7 +227,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64", action="store_true", help="also time the FP64 path on one seed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--quick", action="store_true",
+                    help="one field + one target + a 1 GiB copy, for hardware-counter passes")
     args = ap.parse_args()
+    if args.quick:
+        quick_profile()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU mode "
               "(targets, seeds and realisations shard trivially across GPUs, see the design notes)",

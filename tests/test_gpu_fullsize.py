@@ -1,0 +1,55 @@
+"""Full-size parity: the 256^3 local-NG workload (f_NL = 5, log-normal
+A = 1e-2, sigma = 0.5, k* = 20, 64 log bins) in the launch configuration the
+benchmark times (4 slots, default staging), against FP64 oracle values of
+sampled bins stored in tests/golden/local256_fp64_oracle.json (written by
+tests/golden/make_golden.py, which calls only the oracle).
+
+Bars: FP32 path within 1e-4 relative per sampled bin; FP64 path within
+1e-10; mode counts exact.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2605_27231_amd")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "local256_fp64_oracle.json")) as f:
+        return json.load(f)
+
+
+def _job_matches(g, job):
+    j = g["job"]
+    assert (j["N"], j["A"], j["sigma"], j["k_star"], j["map"], j["F_NL"]) == \
+        (job.N, job.spectrum.A, job.spectrum.sigma, job.spectrum.k_star, job.ngmap.kind, job.ngmap.F_NL)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f64", 1e-10)])
+def test_local256_sampled_bins(prec, tol):
+    g = _golden()
+    job = W.config_local_ng(256, 64)
+    _job_matches(g, job)
+    seeds = sorted({s["seed"] for s in g["samples"]})
+    print(f"full-size 256^3 {prec}: seeds {seeds}", flush=True)
+    with P.Plan(job.N, L=job.L, prec=prec, n_slots=len(job.seeds)) as pl:
+        for seed in seeds:
+            pl.generate_field(seed, seed, job.spectrum, job.ngmap)
+        for seed in seeds:
+            smp = [s for s in g["samples"] if s["seed"] == seed]
+            bins = [s["bin"] for s in smp]
+            om, nb = pl.spectrum(seed, job.targets[bins], job.k_lo[bins], job.k_hi[bins])
+            for s, o, n in zip(smp, om, nb):
+                assert n == s["nmodes"]
+                rel = abs(o - s["omega"]) / abs(s["omega"])
+                print(f"  seed {seed} bin {s['bin']} k={s['target']:.2f} rel err {rel:.2e}", flush=True)
+                assert rel <= tol
