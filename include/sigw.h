@@ -74,7 +74,9 @@ typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2 } si
  * stages at a time (2 half spectra each) before they are expanded into
  * their gradient fields; 0 picks the largest count (up to alpha_chunk) whose
  * staging fits in 16 GiB.  A small count keeps the staging resident in the
- * last-level cache at the price of re-reading Phi_hat per group. */
+ * last-level cache at the price of re-reading Phi_hat per group.  batch is
+ * how many realisations one kernel launch processes together (0 = 1); each
+ * brings its own workspace, so the footprint grows linearly with it. */
 typedef struct {
     int32_t N;
     double  L;
@@ -85,6 +87,7 @@ typedef struct {
     double  u_min, u_max, u_p, sigma_p, A_p;
     int32_t alpha_chunk;
     int32_t scratch_terms;
+    int32_t batch;
 } sigw_plan_desc;
 
 /* Log-normal peak, Eq. lognormal: Delta^2(k) = A/sqrt(2 pi sigma^2) exp(-ln^2(k/k_star)/(2 sigma^2)).
@@ -168,7 +171,8 @@ sigw_status sigw_spectrum(sigw_plan_t plan, int32_t slot, int32_t n_k, const dou
                           int64_t* nmodes_host);
 
 /* The same for several slots that share the targets: omega_host[s * n_k + b]
- * for s = 0..n_sel-1 over slots[s].  Synchronises. */
+ * for s = 0..n_sel-1 over slots[s] (n_sel * n_k <= 4096).  The slots run
+ * `batch` at a time, each group in one launch per kernel.  Synchronises. */
 sigw_status sigw_spectrum_batch(sigw_plan_t plan, int32_t n_sel, const int32_t* slots,
                                 int32_t n_k, const double* k_targets, const double* k_lo,
                                 const double* k_hi, double* omega_host, int64_t* nmodes_host);
@@ -180,6 +184,24 @@ sigw_status sigw_spectrum_batch(sigw_plan_t plan, int32_t n_sel, const int32_t* 
 sigw_status sigw_spectrum_enqueue(sigw_plan_t plan, int32_t slot, int32_t n_k,
                                   const double* k_targets, const double* k_lo, const double* k_hi);
 sigw_status sigw_spectrum_poll(sigw_plan_t plan, double* omega_host, int64_t* nmodes_host);
+
+/* Captured spectra for repeated batches (e.g. ensembles of new realisations
+ * in the same slots): sigw_graph_create records, as one HIP graph on the
+ * plan stream, everything sigw_spectrum_batch would enqueue for these slots
+ * and targets (the plan stream must not be the null stream, and timing must
+ * be off).  sigw_graph_launch replays it on the plan stream for whatever
+ * fields the slots hold at that point; sigw_graph_results synchronises the
+ * plan stream and writes the Omega and N_b of the last replay, laid out as
+ * in sigw_spectrum_batch.  The graph owns its slot list and result buffers;
+ * it shares the plan's workspace, so replays must not overlap other work of
+ * the same plan.  Destroy every graph before its plan. */
+typedef struct sigw_graph* sigw_graph_t;
+sigw_status sigw_graph_create(sigw_plan_t plan, int32_t n_sel, const int32_t* slots, int32_t n_k,
+                              const double* k_targets, const double* k_lo, const double* k_hi,
+                              sigw_graph_t* out);
+sigw_status sigw_graph_launch(sigw_graph_t graph);
+sigw_status sigw_graph_results(sigw_graph_t graph, double* omega_host, int64_t* nmodes_host);
+sigw_status sigw_graph_destroy(sigw_graph_t graph);
 
 /* Block until the plan stream is idle. */
 sigw_status sigw_synchronize(sigw_plan_t plan);

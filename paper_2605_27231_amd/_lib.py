@@ -31,6 +31,7 @@ EXPORTS = (
     "sigw_set_phi_hat", "sigw_get_phi_hat", "sigw_source_convolutions", "sigw_spectrum",
     "sigw_spectrum_batch", "sigw_spectrum_enqueue", "sigw_spectrum_poll", "sigw_synchronize",
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
+    "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
 )
 
 
@@ -40,7 +41,7 @@ class PlanDesc(ct.Structure):
         ("n_modes", ct.c_int32), ("n_alpha", ct.c_int32),
         ("u_min", ct.c_double), ("u_max", ct.c_double), ("u_p", ct.c_double),
         ("sigma_p", ct.c_double), ("A_p", ct.c_double), ("alpha_chunk", ct.c_int32),
-        ("scratch_terms", ct.c_int32),
+        ("scratch_terms", ct.c_int32), ("batch", ct.c_int32),
     ]
 
 
@@ -95,6 +96,10 @@ def lib() -> ct.CDLL:
         "sigw_kernel_time": [P, ct.c_char_p, D, I64],
         "sigw_last_error": [P],
         "sigw_status_string": [ct.c_int],
+        "sigw_graph_create": [P, ct.c_int32, I32, ct.c_int32, D, D, D, ct.POINTER(P)],
+        "sigw_graph_launch": [P],
+        "sigw_graph_results": [P, D, I64],
+        "sigw_graph_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -32,13 +32,14 @@ def _i64ptr(a: np.ndarray):
 def plan_desc(N: int, L: float = 2 * math.pi, prec: str = "f32", n_slots: int = 1,
               n_modes: int = 200, n_alpha: int = 50, u_min: float = 1e-3, u_max: float = 15.0,
               u_p: float = 1.0, sigma_p: float = 0.5, A_p: float = 10.0,
-              alpha_chunk: int = 0, scratch_terms: int = 0) -> _lib.PlanDesc:
+              alpha_chunk: int = 0, scratch_terms: int = 0, batch: int = 0) -> _lib.PlanDesc:
     d = _lib.PlanDesc()
     d.N, d.L, d.prec, d.n_slots = N, L, _prec_code(prec), n_slots
     d.n_modes, d.n_alpha = n_modes, n_alpha
     d.u_min, d.u_max, d.u_p, d.sigma_p, d.A_p = u_min, u_max, u_p, sigma_p, A_p
     d.alpha_chunk = alpha_chunk
     d.scratch_terms = scratch_terms
+    d.batch = batch
     return d
 
 
@@ -196,6 +197,9 @@ class Plan:
         self._chk(st, "sigw_spectrum_poll")
         return om, nb
 
+    def graph(self, slots: Sequence[int], targets, k_lo, k_hi) -> "SpectrumGraph":
+        return SpectrumGraph(self, slots, targets, k_lo, k_hi)
+
     # -- timing --------------------------------------------------------------
     def set_timing(self, on: bool):
         self._chk(lib().sigw_set_timing(self.h, 1 if on else 0), "sigw_set_timing")
@@ -209,3 +213,41 @@ class Plan:
 
     def synchronize(self):
         self._chk(lib().sigw_synchronize(self.h), "sigw_synchronize")
+
+
+class SpectrumGraph:
+    """A captured batched spectrum (sigw_graph_t): replay it after refilling
+    the same slots with new fields."""
+
+    def __init__(self, plan: Plan, slots, targets, k_lo, k_hi):
+        self.plan = plan
+        self.t = np.ascontiguousarray(targets, dtype=np.float64)
+        self.lo = np.ascontiguousarray(k_lo, dtype=np.float64)
+        self.hi = np.ascontiguousarray(k_hi, dtype=np.float64)
+        self.sl = np.ascontiguousarray(slots, dtype=np.int32)
+        h = ct.c_void_p()
+        st = lib().sigw_graph_create(plan.h, len(self.sl), self.sl.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                     len(self.t), _dptr(self.t), _dptr(self.lo), _dptr(self.hi),
+                                     ct.byref(h))
+        check(st, plan.h, "sigw_graph_create")
+        self.h = h
+
+    def launch(self):
+        check(lib().sigw_graph_launch(self.h), self.plan.h, "sigw_graph_launch")
+
+    def results(self):
+        om = np.zeros((len(self.sl), len(self.t)))
+        nb = np.zeros((len(self.sl), len(self.t)), dtype=np.int64)
+        check(lib().sigw_graph_results(self.h, _dptr(om), _i64ptr(nb)), self.plan.h, "sigw_graph_results")
+        return om, nb
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sigw_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,9 +31,10 @@ struct Engine {
     // Inverse DFT along x of a half spectrum into a real field.
     virtual void xpass_c2r(const void* half_in, void* real_out, hipStream_t s) = 0;
     // Complex DFT along y, in place, of n_fields half spectra spaced by
-    // field_stride complex elements, on the kx planes [0, n_planes).
-    virtual void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign,
-                       hipStream_t s) = 0;
+    // field_stride complex elements, on the kx planes [0, n_planes), for nb
+    // batch members spaced by batch_stride.
+    virtual void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign, int nb,
+                       long batch_stride, hipStream_t s) = 0;
     // Complex DFT along z, in place, of n_rows contiguous rows.
     virtual void zpass(void* data, long n_rows, int sign, hipStream_t s) = 0;
     // Multiply a half spectrum by amp[|n|^2] (FP64 table, rounded to the path precision).
@@ -48,27 +49,37 @@ struct Engine {
     // k_lo <= k_F sqrt(n2) < k_hi, n2 > 0.
     virtual void lut(double k_F, double k_target, double k_lo, double k_hi, const double* edges,
                      int n_modes, int16_t* lut_u, uint8_t* lut_shell, hipStream_t s) = 0;
+    // Every per-target kernel below runs nb batch members in one launch
+    // (grid y); member b works on the realisation in slot sel[b] and on its
+    // own workspace, found at b times the given stride.
+    //
     // Fused weighting + inverse DFT along z: for a = a0..a0+na-1,
     // S[2(a-a0)] = IDFT_z( phi_a(u) Phi_hat / V ), S[2(a-a0)+1] = IDFT_z( i qt_z phi_a(u) Phi_hat / V ).
-    virtual void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab,
-                       int n_alpha, int a0, int na, double k_F, double inv_V, void* S,
-                       hipStream_t s) = 0;
+    virtual void gen_z(const void* phi_hat_slots, const int* sel, int nb, const int16_t* lut_u,
+                       const void* phi_tab, int n_alpha, int a0, int na, double k_F, double inv_V,
+                       void* S, long s_stride, hipStream_t s) = 0;
     // Inverse DFT along y of na terms' (W, Z) pairs into their three gradient
     // fields T[3a + j]: IDFT_y(W), IDFT_y(i qt_y W), IDFT_y(Z).
-    virtual void ypass3(const void* S, int na, void* T, double k_F, hipStream_t s) = 0;
+    virtual void ypass3(const void* S, int na, int nb, long s_stride, void* T, long t_stride, double k_F,
+                        hipStream_t s) = 0;
     // Fused inverse DFT along x (with i qt_x on the first field of each term)
     // + products + forward DFT along x:
     // Qx_c = DFT_x( sum_a sigma_a dV G_a,i G_a,j ) for the 6 components, on
     // the kx planes [0, n_planes); accumulate adds into Qx instead of storing.
-    virtual void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, double k_F,
-                       void* Qx, int n_planes, int accumulate, hipStream_t s) = 0;
+    virtual void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na,
+                       double dV, double k_F, void* Qx, long q_stride, int n_planes, int accumulate,
+                       hipStream_t s) = 0;
     // Fused forward DFT along z of the 12 components (both kernels) + TT
-    // projection + shell sums: one (sum, count) partial per block.
-    virtual void zbin(const void* Qxy, const uint8_t* lut_shell, int n2_lo, int n2_hi,
-                      double* partial_sum, unsigned long long* partial_cnt, hipStream_t s) = 0;
-    // Fixed-order reduction of n partials into out_sum[0], out_cnt[0].
-    virtual void finalize(const double* partial_sum, const unsigned long long* partial_cnt, int n,
-                          double* out_sum, unsigned long long* out_cnt, hipStream_t s) = 0;
+    // projection + shell sums: one (sum, count) partial per block, member b's
+    // at [b * zbin_blocks(), (b + 1) * zbin_blocks()).
+    virtual void zbin(const void* Qxy, int nb, long q_stride, const uint8_t* lut_shell, int n2_lo,
+                      int n2_hi, double* partial_sum, unsigned long long* partial_cnt,
+                      hipStream_t s) = 0;
+    // Fixed-order reduction of each member's n partials into
+    // out_sum[b * out_stride], out_cnt[b * out_stride].
+    virtual void finalize(const double* partial_sum, const unsigned long long* partial_cnt, int n, int nb,
+                          double* out_sum, unsigned long long* out_cnt, int out_stride,
+                          hipStream_t s) = 0;
 };
 
 // Returns nullptr for an unsupported (prec, N).

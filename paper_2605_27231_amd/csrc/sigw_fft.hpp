@@ -250,14 +250,24 @@ template <> struct TwoPhase<512> { static constexpr int R1 = 16; };
 template <int N, int NL, bool LINE_FAST> struct TPLayout {
     static constexpr int R1 = TwoPhase<N>::R1;
     static constexpr int R2 = N / R1;
-    static constexpr int size = LINE_FAST ? NL * N : NL * R1 * (R2 + 1);
+    // LINE_FAST rows of one k1 hold R2 * NL elements.  When NL is not a
+    // multiple of 16, the 16 lanes the LDS serves together span two k1 rows;
+    // pad each row so that the next one starts NL elements further along the
+    // banks (row stride = NL mod 32 elements) and those lanes do not collide.
+    static constexpr int PADK = (NL % 16 == 0) ? 0 : ((NL - (R2 * NL) % 32) % 32 + 32) % 32;
+    static constexpr int RS = R2 * NL + PADK;
+    static constexpr int size = LINE_FAST ? R1 * RS : NL * R1 * (R2 + 1);
     __device__ static __forceinline__ int at(int line, int k1, int t) {
-        return LINE_FAST ? (k1 * R2 + t) * NL + line : (line * R1 + k1) * (R2 + 1) + t;
+        return LINE_FAST ? k1 * RS + t * NL + line : (line * R1 + k1) * (R2 + 1) + t;
     }
 };
 
+// Phase 1.  tw serves the register DFT's own twiddles (fixed indices, read
+// through the scalar cache); twv serves the inter-phase twiddles
+// tw[t k1], whose index depends on the lane: a copy of the table in LDS
+// keeps those off the vector memory path.
 template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
-__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, int tid) {
+__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, const C* twv, int tid) {
     using Lay = TPLayout<N, NL, LINE_FAST>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = NL * R2;
@@ -274,11 +284,24 @@ __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 C v = a[k1];
-                if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(tw, t * k1));
+                if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(twv, t * k1));
                 lds[Lay::at(line, k1, t)] = v;
             }
         }
     }
+}
+
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
+__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, int tid) {
+    tp_phase1<C, N, SIGN, NL, NT, LINE_FAST>(ld, lds, tw, tw, tid);
+}
+
+// Copy of the N-entry twiddle table into LDS, for the lane-dependent twiddles
+// of phase 1 (the caller synchronises before use).
+template <typename C, int N, int NT>
+__device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw, int tid) {
+#pragma unroll
+    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
 }
 
 template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class ST>

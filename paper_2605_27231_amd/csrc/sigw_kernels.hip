@@ -237,7 +237,8 @@ template <typename R, int N> struct YCfg {
 
 template <typename R, int N, int SIGN>
 __global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict__ data, long field_stride,
-                                               int n_planes, const typename CplxOf<R>::T* __restrict__ tw) {
+                                               int n_planes, long batch_stride,
+                                               const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     constexpr int TZ = YCfg<R, N>::TZ;
     constexpr int NT = YCfg<R, N>::NT;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict
     const long fp = b / NZC;
     const int kx = int(fp % n_planes);
     const long f = fp / n_planes;
-    C* base = data + f * field_stride + long(kx) * N * N + zc * TZ;
+    C* base = data + blockIdx.y * batch_stride + f * field_stride + long(kx) * N * N + zc * TZ;
     auto ld = [&](int zz, int y) -> C { return base[long(y) * N + zz]; };
     auto st = [&](int zz, int y, C v) { base[long(y) * N + zz] = v; };
     tp_phase1<C, N, SIGN, TZ, NT, true>(ld, lds, tw, tid);
@@ -462,10 +463,10 @@ template <typename R, int N> struct GCfg {
 };
 
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __restrict__ phi_hat,
-                                               const int16_t* __restrict__ lut_u, const R* __restrict__ phi_tab,
-                                               int n_alpha, int a0, int na, R k_F, R inv_V,
-                                               typename CplxOf<R>::T* __restrict__ T,
+__global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __restrict__ phi_hat_all,
+                                               const int* __restrict__ sel, const int16_t* __restrict__ lut_u,
+                                               const R* __restrict__ phi_tab, int n_alpha, int a0, int na, R k_F,
+                                               R inv_V, typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
                                                const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using G = GCfg<R, N>;
@@ -478,6 +479,9 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
     __shared__ C lds[Lay::size];
     const int tid = threadIdx.x;
     const long row0 = long(blockIdx.x) * RB;
+    // batch member blockIdx.y works on the realisation in slot sel[blockIdx.y]
+    const C* phi_hat = phi_hat_all + long(sel[blockIdx.y]) * FS;
+    C* T = S_all + blockIdx.y * s_stride;
     C ph[PER][R1];
     int16_t idx[PER][R1];
 #pragma unroll
@@ -546,14 +550,15 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
 // ----------------------------------------------------------------------------
 // ypass3: inverse DFT along y that expands the two z-transformed fields of
 // each term into its three gradient fields:
-//   U_x = IDFT_y(W_a),  U_y = IDFT_y(i qt_y W_a),  U_z = IDFT_y(Z_a)
-// (U_x still lacks its factor i qt_x, applied by the x pass).  Tile (term,
+//   U_x = i qt_x IDFT_y(W_a),  U_y = IDFT_y(i qt_y W_a),  U_z = IDFT_y(Z_a)
+// (qt_x is uniform over a block's kx plane, so its factor costs nothing
+// here and leaves the x pass a uniform Hermitian extension).  Tile (term,
 // kx plane, z chunk); the three outputs are transformed one after another
 // through the same LDS tile.
 // ----------------------------------------------------------------------------
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __restrict__ S,
-                                                typename CplxOf<R>::T* __restrict__ T, R k_F,
+__global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
+                                                typename CplxOf<R>::T* __restrict__ T_all, long t_stride, R k_F,
                                                 const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     constexpr int TZ = YCfg<R, N>::TZ;
@@ -562,30 +567,39 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     constexpr int H = N / 2 + 1;
     constexpr long FS = Shape<R, N>::FS;
     __shared__ C lds[TPLayout<N, TZ, true>::size];
+    __shared__ C twl[N];
     const int tid = threadIdx.x;
+    stage_twiddles<C, N, NT>(twl, tw, tid);
+    __syncthreads();
     const long b = blockIdx.x;
     const int zc = int(b % NZC);
     const long fp = b / NZC;
     const int kx = int(fp % H);
     const long al = fp / H;
     const long off = long(kx) * N * N + zc * TZ;
+    const C* S = S_all + blockIdx.y * s_stride;
+    C* T = T_all + blockIdx.y * t_stride;
     const C* w = S + 2 * al * FS + off;
     const C* z = w + FS;
+    const R qx = (kx == N / 2) ? R(0) : k_F * R(kx);     // qt_x of this plane
 #pragma unroll 1
     for (int j = 0; j < 3; ++j) {
         const C* src = j == 2 ? z : w;
         C* dst = T + (3 * al + j) * FS + off;
         auto ld = [&](int zz, int y) -> C {
             C v = src[long(y) * N + zz];
-            if (j == 1) {
-                const int ny = signed_index(y, N);
-                const R q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+            if (j < 2) {
+                R q = qx;
+                if (j == 1) {
+                    const int ny = signed_index(y, N);
+                    q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+                }
                 v = cmk<C>(-q * v.y, q * v.x);
             }
             return v;
         };
         auto st = [&](int zz, int y, C v) { dst[long(y) * N + zz] = v; };
-        tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, tw, tid);
+        tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, tw, twl, tid);
         __syncthreads();
         tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tw, tid);
         __syncthreads();
@@ -601,14 +615,15 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
 // once, coalesced, straight from global memory into LDS by the gfx950
 // global-to-LDS loads (no registers involved), double buffered: the tile of
 // term a+1 is in flight while term a is transformed and multiplied.  The
-// Hermitian extension of the x lines (and the factor i qt_x of the first
-// field) is applied when phase 1 reads the tile back.
+// Hermitian extension of the x lines is applied when phase 1 reads the tile
+// back (the gradient factors were applied by the earlier passes).
 // ----------------------------------------------------------------------------
 template <typename R, int N>
-__global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* __restrict__ T, const R* __restrict__ sigma,
-                                               int a0, int na, R dV, R k_F, typename CplxOf<R>::T* __restrict__ Qx,
-                                               int n_planes, int accumulate,
-                                               const typename CplxOf<R>::T* __restrict__ tw) {
+__global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
+                                                  const R* __restrict__ sigma, int a0, int na, R dV, R k_F,
+                                                  typename CplxOf<R>::T* __restrict__ Q_all, long q_stride,
+                                                  int n_planes, int accumulate,
+                                                  const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using S = Shape<R, N>;
     constexpr int TZ = S::TZX;
@@ -618,16 +633,22 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
     constexpr int NZC = N / TZ;
     constexpr int H = N / 2 + 1;
     constexpr long FS = S::FS;
-    constexpr int LS = N + 1;
+    // line stride of the G / Q lines: N + 2 keeps lanes that store the same
+    // x of neighbouring lines (and neighbouring k1 of one line) on distinct banks
+    constexpr int LS = N + 2;
     constexpr int NLI = 3 * P;                                   // inverse lines (field, z pair)
     constexpr int NRAW = 3 * H * P;                              // raw pairs per term
     constexpr int TRS = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
     __shared__ C raw[2][2 * NRAW];                               // [buffer][field][kx][pair][2]
     __shared__ C Z[TRS];                                         // transpose, then G lines
+    __shared__ C twl[N];
     const int tid = threadIdx.x;
+    stage_twiddles<C, N, NT>(twl, tw, tid);
     const int zc = blockIdx.x % NZC;
     const int y = blockIdx.x / NZC;
     const int z0 = zc * TZ;
+    const C* T = T_all + blockIdx.y * t_stride;
+    C* Qx = Q_all + blockIdx.y * q_stride;
     C Q[6][PP];
 #pragma unroll
     for (int c = 0; c < 6; ++c)
@@ -638,41 +659,85 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
     // 16-byte units: a raw element (two complex) is 1 unit in FP32, 2 in FP64
     constexpr int UPE = int(2 * sizeof(C) / 16);
     constexpr int NU = NRAW * UPE;
+    constexpr int NIT = (NU + NT - 1) / NT;
     static_assert(NT % 64 == 0 || NT < 64, "global-to-LDS loads are issued per whole wavefront");
+    static_assert((3 * FS) * long(sizeof(C)) < (1L << 32), "tile offsets are 32-bit");
+    const int lane = tid & 63;
+    // byte offset of this lane's unit in each load round, relative to the
+    // term's first field: the same for every term
+    unsigned uoff[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int u = tid + i * NT;
+        const int e = u / UPE, h = u - e * UPE;
+        const int j = e / (H * P);
+        const int rem = e - j * (H * P);
+        const int k = rem / P, p = rem - k * P;
+        uoff[i] = unsigned((long(j) * FS + long(k) * N * N + 2 * p) * long(sizeof(C)) + 16 * h);
+    }
     auto issue_tile = [&](int a, C* dst) {
         const char* colf = reinterpret_cast<const char*>(col0 + long(3 * (a - a0)) * FS);
         char* dstb = reinterpret_cast<char*>(dst);
-        const int lane = tid & 63;
-        for (int u0 = tid - lane; u0 < NU; u0 += NT) {       // u0 is uniform in the wavefront
-            const int u = u0 + lane;
-            if (u < NU) {
-                const int e = u / UPE, h = u - e * UPE;
-                const int j = e / (H * P);
-                const int rem = e - j * (H * P);
-                const int k = rem / P, p = rem - k * P;
-                const char* src = colf + (long(j) * FS + long(k) * N * N + 2 * p) * long(sizeof(C)) + 16 * h;
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int u0 = tid - lane + i * NT;               // uniform in the wavefront
+            if (u0 < NU && (i < NIT - 1 || u0 + lane < NU)) {
                 // lane i of the wavefront lands at dstb + 16 (u0 + i)
-                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(colf + uoff[i]),
                                                  (__attribute__((address_space(3))) void*)(dstb + 16L * u0), 16, 0,
                                                  0);
             }
         }
     };
     const C* rawc = raw[0];
-    // element n of inverse line (j, p), from the raw tile
-    auto ld = [&](int line, int n) -> C {
-        const int j = line / P, p = line % P;
-        const int k = n <= N / 2 ? n : N - n;
-        const int e = (j * H + k) * P + p;
-        C a = rawc[2 * e], b = rawc[2 * e + 1];
-        const bool edge = (k == 0 || k == N / 2);
-        const bool grad = (j == 0);
-        const R q = (grad && !edge) ? k_F * R(k) : R(0);
-        const R keep = grad ? R(0) : R(1);
-        const R ky = edge ? R(0) : keep;
-        a = cmk<C>(keep * a.x - q * a.y, ky * a.y + q * a.x);
-        b = cmk<C>(keep * b.x - q * b.y, ky * b.y + q * b.x);
-        return n <= N / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
+    using LayI = TPLayout<N, NLI, true>;
+    constexpr int R1 = LayI::R1, R2 = LayI::R2;
+    constexpr int ITEMS1 = NLI * R2;
+    static_assert(R1 % 2 == 0, "the Hermitian split below assumes an even first radix");
+    // phase 1 of the inverse x transform.  Item w -> (j, t, p) with p
+    // fastest, then t, then j.  Element n = t + R2 m of inverse line (j, p)
+    // packs the z pair (2p, 2p+1) as A + i B, with A, B read at kx = n for
+    // m < R1/2 (n < N/2) and conjugated from kx = N - n for m >= R1/2
+    // (for n = N/2 both readings agree once the imaginary parts are gone).
+    // On the self-conjugate planes kx = 0 and N/2 the imaginary parts are
+    // dropped (real-input convention).
+    auto phase1 = [&]() {
+#pragma unroll
+        for (int w0 = 0; w0 < ITEMS1; w0 += NT) {
+            const int w = w0 + tid;
+            if ((ITEMS1 % NT == 0) || w < ITEMS1) {
+                const int p = w % P;
+                const int t = (w / P) % R2;
+                const int j = w / (P * R2);
+                const C* lo = rawc + 2 * ((j * H + t) * P + p);              // kx = t
+                const C* hb = rawc + 2 * ((j * H + N / 2 - t) * P + p);      // kx = N/2 - t
+                const bool t0 = (t == 0);
+                C v[R1];
+#pragma unroll
+                for (int m = 0; m < R1; ++m) {
+                    C a, b;
+                    if (m < R1 / 2) {                                        // kx = t + R2 m
+                        a = lo[2 * P * R2 * m];
+                        b = lo[2 * P * R2 * m + 1];
+                    } else {                                                 // kx = N/2 - t - R2 (m - R1/2)
+                        a = hb[-2 * P * R2 * (m - R1 / 2)];
+                        b = hb[-2 * P * R2 * (m - R1 / 2) + 1];
+                    }
+                    if ((m == 0 || m == R1 / 2) && t0) {
+                        a.y = R(0);
+                        b.y = R(0);
+                    }
+                    v[m] = m < R1 / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
+                }
+                reg_dft<R1, +1, N>(v, tw);
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) {
+                    C o = v[k1];
+                    if (k1 > 0) o = cmul(o, tw_at<+1, N>(twl, t * k1));
+                    Z[LayI::at(j * P + p, k1, t)] = o;
+                }
+            }
+        }
     };
 
     issue_tile(a0, raw[0]);
@@ -680,10 +745,15 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
         const int cur = (a - a0) & 1;
         __builtin_amdgcn_s_waitcnt(0);    // this wavefront's loads of tile a have landed
         __syncthreads();                  // ... and every wavefront's; Z is free again
-        if (a + 1 < a0 + na) issue_tile(a + 1, raw[cur ^ 1]);
         rawc = raw[cur];
-        tp_phase1<C, N, +1, NLI, NT, true>(ld, Z, tw, tid);
+        phase1();
         __syncthreads();
+        // the next tile is requested after phase 1, so that its LDS writes
+        // overlap phase 2 and the products rather than phase 1's tile reads
+        // (measured faster).  Phase 1 makes no vector memory access: its
+        // twiddles come from LDS, because such an access would complete only
+        // after every tile load in flight.
+        if (a + 1 < a0 + na) issue_tile(a + 1, raw[cur ^ 1]);
         TPRegs<C, N, +1, NLI, NT, true> g;
         g.run(Z, tw, tid);
         __syncthreads();
@@ -706,8 +776,8 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
             Q[4][i] = cmk<C>(Q[4][i].x + sx.x * gz.x, Q[4][i].y + sx.y * gz.y);
             Q[5][i] = cmk<C>(Q[5][i].x + sy.x * gz.x, Q[5][i].y + sy.y * gz.y);
         }
-        // tile a+2 goes into raw[cur] only after the next barrier, when
-        // phase 1 of this term has long finished reading it
+        // tile a+2 goes into raw[cur] only after phase 1 of term a+1, long
+        // after phase 1 of this term finished reading it
     }
     __syncthreads();
     // forward DFT along x, one component at a time: the P pair lines are
@@ -722,7 +792,7 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
             zq[(qq / N) * LS + (qq % N)] = Q[c][i];
         }
         __syncthreads();
-        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, tw, tid);
+        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, tw, twl, tid);
         __syncthreads();
         TPRegs<C, N, -1, P, NT, false> f;
         f.run(zt, tw, tid);
@@ -794,7 +864,7 @@ __device__ __forceinline__ double tt_power(const double2* X /* 6 comps */, doubl
 }
 
 template <typename R, int N>
-__global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __restrict__ Qxy,
+__global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __restrict__ Q_all, long q_stride,
                                               const uint8_t* __restrict__ lut_shell, int n2_lo, int n2_hi,
                                               double* __restrict__ part_sum,
                                               unsigned long long* __restrict__ part_cnt,
@@ -811,6 +881,7 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
     __shared__ unsigned long long rcnt[NT / 64];
     const int tid = threadIdx.x;
     const long row0 = long(blockIdx.x) * RB;
+    const C* Qxy = Q_all + blockIdx.y * q_stride;
     // can any row of this block reach the shell?
     bool any = false;
     for (int r = 0; r < RB; ++r) {
@@ -880,17 +951,20 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
             t += rsum[i];
             c += rcnt[i];
         }
-        part_sum[blockIdx.x] = t;
-        part_cnt[blockIdx.x] = c;
+        part_sum[long(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+        part_cnt[long(blockIdx.y) * gridDim.x + blockIdx.x] = c;
     }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ ps, const unsigned long long* __restrict__ pc,
-                                                  int n, double* __restrict__ out_sum,
-                                                  unsigned long long* __restrict__ out_cnt) {
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ ps_all,
+                                                  const unsigned long long* __restrict__ pc_all, int n,
+                                                  double* __restrict__ out_sum, unsigned long long* __restrict__ out_cnt,
+                                                  int out_stride) {
     __shared__ double rs[256];
     __shared__ unsigned long long rc[256];
     const int tid = threadIdx.x;
+    const double* ps = ps_all + long(blockIdx.x) * n;
+    const unsigned long long* pc = pc_all + long(blockIdx.x) * n;
     double a = 0.0;
     unsigned long long c = 0ull;
     for (int i = tid; i < n; i += 256) {
@@ -908,8 +982,8 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ ps,
         __syncthreads();
     }
     if (tid == 0) {
-        out_sum[0] = rs[0];
-        out_cnt[0] = rc[0];
+        out_sum[long(blockIdx.x) * out_stride] = rs[0];
+        out_cnt[long(blockIdx.x) * out_stride] = rc[0];
     }
 }
 
@@ -940,13 +1014,17 @@ template <typename R, int NN> struct EngineImpl final : Engine {
         k_xpass_c2r<R, NN><<<dim3(NN * (NN / S::TZ)), dim3(XCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(in),
                                                                       static_cast<R*>(out), tw);
     }
-    void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign, hipStream_t s) override {
+    void ypass(void* data, int n_fields, long field_stride, int n_planes, int sign, int nb, long batch_stride,
+               hipStream_t s) override {
         const unsigned blocks = unsigned(long(n_fields) * n_planes * (NN / S::TZ));
-        if (blocks == 0) return;
+        if (blocks == 0 || nb <= 0) return;
+        const dim3 grid(blocks, unsigned(nb));
         if (sign < 0)
-            k_ypass<R, NN, -1><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+            k_ypass<R, NN, -1><<<grid, dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes,
+                                                                      batch_stride, tw);
         else
-            k_ypass<R, NN, +1><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes, tw);
+            k_ypass<R, NN, +1><<<grid, dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<C*>(data), field_stride, n_planes,
+                                                                      batch_stride, tw);
     }
     void zpass(void* data, long n_rows, int sign, hipStream_t s) override {
         const unsigned blocks = unsigned((n_rows + ZCfg<R, NN>::RB - 1) / ZCfg<R, NN>::RB);
@@ -976,34 +1054,35 @@ template <typename R, int NN> struct EngineImpl final : Engine {
         k_lut<<<dim3(unsigned(n2max / 256 + 1)), dim3(256), 0, s>>>(n2max, k_F, k_target, k_lo, k_hi, edges,
                                                                     n_modes, lut_u, lut_shell);
     }
-    void gen_z(const void* phi_hat, const int16_t* lut_u, const void* phi_tab, int n_alpha, int a0, int na,
-               double k_F, double inv_V, void* T, hipStream_t s) override {
+    void gen_z(const void* phi_hat, const int* sel, int nb, const int16_t* lut_u, const void* phi_tab, int n_alpha,
+               int a0, int na, double k_F, double inv_V, void* Sd, long s_stride, hipStream_t s) override {
         const unsigned blocks = unsigned((long(S::H) * NN) / GCfg<R, NN>::RB);
-        k_gen_z<R, NN><<<dim3(blocks), dim3(GCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(phi_hat), lut_u,
-                                                        static_cast<const R*>(phi_tab), n_alpha, a0, na,
-                                                        R(k_F), R(inv_V), static_cast<C*>(T), tw);
+        k_gen_z<R, NN><<<dim3(blocks, unsigned(nb)), dim3(GCfg<R, NN>::NT), 0, s>>>(
+            static_cast<const C*>(phi_hat), sel, lut_u, static_cast<const R*>(phi_tab), n_alpha, a0, na, R(k_F),
+            R(inv_V), static_cast<C*>(Sd), s_stride, tw);
     }
-    void ypass3(const void* Sd, int na, void* T, double k_F, hipStream_t s) override {
+    void ypass3(const void* Sd, int na, int nb, long s_stride, void* T, long t_stride, double k_F,
+                hipStream_t s) override {
         const unsigned blocks = unsigned(long(na) * S::H * (NN / YCfg<R, NN>::TZ));
-        if (blocks == 0) return;
-        k_ypass3<R, NN><<<dim3(blocks), dim3(YCfg<R, NN>::NT), 0, s>>>(static_cast<const C*>(Sd),
-                                                                      static_cast<C*>(T), R(k_F), tw);
+        if (blocks == 0 || nb <= 0) return;
+        k_ypass3<R, NN><<<dim3(blocks, unsigned(nb)), dim3(YCfg<R, NN>::NT), 0, s>>>(
+            static_cast<const C*>(Sd), s_stride, static_cast<C*>(T), t_stride, R(k_F), tw);
     }
-    void xprod(const void* T, const void* sigma_tab, int a0, int na, double dV, double k_F, void* Qx,
-               int n_planes, int accumulate, hipStream_t s) override {
+    void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na, double dV, double k_F,
+               void* Qx, long q_stride, int n_planes, int accumulate, hipStream_t s) override {
         const unsigned blocks = unsigned(NN * (NN / S::TZX));
-        k_xprod<R, NN><<<dim3(blocks), dim3(S::NTX), 0, s>>>(static_cast<const C*>(T),
-                                                           static_cast<const R*>(sigma_tab), a0, na, R(dV),
-                                                           R(k_F), static_cast<C*>(Qx), n_planes, accumulate, tw);
+        k_xprod<R, NN><<<dim3(blocks, unsigned(nb)), dim3(S::NTX), 0, s>>>(
+            static_cast<const C*>(T), t_stride, static_cast<const R*>(sigma_tab), a0, na, R(dV), R(k_F),
+            static_cast<C*>(Qx), q_stride, n_planes, accumulate, tw);
     }
-    void zbin(const void* Qxy, const uint8_t* lut_shell, int n2_lo, int n2_hi, double* ps,
+    void zbin(const void* Qxy, int nb, long q_stride, const uint8_t* lut_shell, int n2_lo, int n2_hi, double* ps,
               unsigned long long* pc, hipStream_t s) override {
-        k_zbin<R, NN><<<dim3(unsigned(zbin_blocks())), dim3(256), 0, s>>>(static_cast<const C*>(Qxy), lut_shell,
-                                                                         n2_lo, n2_hi, ps, pc, tw);
+        k_zbin<R, NN><<<dim3(unsigned(zbin_blocks()), unsigned(nb)), dim3(256), 0, s>>>(
+            static_cast<const C*>(Qxy), q_stride, lut_shell, n2_lo, n2_hi, ps, pc, tw);
     }
-    void finalize(const double* ps, const unsigned long long* pc, int n, double* out_sum,
-                  unsigned long long* out_cnt, hipStream_t s) override {
-        k_finalize<<<dim3(1), dim3(256), 0, s>>>(ps, pc, n, out_sum, out_cnt);
+    void finalize(const double* ps, const unsigned long long* pc, int n, int nb, double* out_sum,
+                  unsigned long long* out_cnt, int out_stride, hipStream_t s) override {
+        k_finalize<<<dim3(unsigned(nb)), dim3(256), 0, s>>>(ps, pc, n, out_sum, out_cnt, out_stride);
     }
 };
 

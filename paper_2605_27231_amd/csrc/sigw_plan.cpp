@@ -172,6 +172,7 @@ const char* validate(const sigw_plan_desc* d) {
     if (!(d->sigma_p > 0.0) || !(d->A_p >= 0.0) || !std::isfinite(d->u_p)) return "need sigma_p > 0, A_p >= 0";
     if (d->alpha_chunk < 0 || d->alpha_chunk > d->n_alpha) return "alpha_chunk must be in [0, n_alpha]";
     if (d->scratch_terms < 0 || d->scratch_terms > d->n_alpha) return "scratch_terms must be in [0, n_alpha]";
+    if (d->batch < 0 || d->batch > 4096) return "batch must be in [0, 4096]";
     return nullptr;
 }
 
@@ -180,6 +181,7 @@ struct Sizes {
     size_t cb, rb;
     int chunk;     // terms per xprod pass (workspace T holds 3 * chunk fields)
     int stage;     // terms staged per gen_z / ypass3 pair (scratch holds 2 * stage fields)
+    int batch;     // realisations per launch (each has its own S, T and Q workspace)
 };
 
 // Default staging: every term of a pass at once when the (W, Z) pairs fit in
@@ -196,6 +198,7 @@ Sizes sizes_of(const sigw_plan_desc& d) {
     z.rb = d.prec == SIGW_F64 ? 8 : 4;
     z.cb = 2 * z.rb;
     z.chunk = d.alpha_chunk == 0 ? d.n_alpha : d.alpha_chunk;
+    z.batch = d.batch == 0 ? 1 : d.batch;
     if (d.scratch_terms > 0) {
         z.stage = std::min(d.scratch_terms, z.chunk);
     } else {
@@ -217,12 +220,12 @@ size_t footprint_of(const sigw_plan_desc& d) {
     b += 2 * size_t(d.n_modes) * d.n_alpha * z.rb + 2 * size_t(d.n_alpha) * z.rb;
     b += size_t(z.n2max + 1) * (2 + 1 + 8);                    // lut_u, lut_shell, amp
     b += size_t(d.n_slots) * z.FS * z.cb;                      // Phi_hat per slot
-    b += size_t(3) * z.chunk * z.FS * z.cb;                    // gradient-field workspace
-    b += size_t(2) * z.stage * z.FS * z.cb;                    // staged (W, Z) pairs
-    b += size_t(12) * z.FS * z.cb;                             // Q components (both kernels)
+    b += size_t(z.batch) * 3 * z.chunk * z.FS * z.cb;          // gradient-field workspace
+    b += size_t(z.batch) * 2 * z.stage * z.FS * z.cb;          // staged (W, Z) pairs
+    b += size_t(z.batch) * 12 * z.FS * z.cb;                   // Q components (both kernels)
     b += size_t(z.R3) * z.rb;                                  // real scratch
-    b += size_t(zb) * 16 + size_t(kSumsqBlocks + 1) * 8;       // partials
-    b += size_t(kMaxTargets) * 16;                             // per-target sums
+    b += size_t(z.batch) * zb * 16 + size_t(kSumsqBlocks + 1) * 8;   // partials
+    b += size_t(kMaxTargets) * (16 + 4);                       // per-target sums, slot list
     return b;
 }
 
@@ -263,6 +266,10 @@ struct sigw_plan {
     double* h_amp = nullptr;
     hipEvent_t amp_ev = nullptr;
     bool amp_inflight = false;
+    int* h_sel = nullptr;       // staged slot list of the last enqueued spectrum
+    int* d_sel = nullptr;
+    hipEvent_t sel_ev = nullptr;
+    bool sel_inflight = false;
     double* h_sums = nullptr;
     unsigned long long* h_cnts = nullptr;
     std::vector<char> has_field;
@@ -359,39 +366,58 @@ bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n
     return true;
 }
 
-// Enqueue the convolutions of one target for one slot, leaving the 12
-// components after the forward y pass in p->Q (planes [0, n_planes)).
-sigw_status enqueue_convolutions(sigw_plan* p, int slot, double k_target, int n_planes) {
+// Enqueue the convolutions of one target for nb realisations (the slots at
+// sel_dev[0..nb)), leaving each member's 12 components after the forward y
+// pass in its Q workspace (planes [0, n_planes)).
+sigw_status enqueue_convolutions(sigw_plan* p, const int* sel_dev, int nb, double k_target, int n_planes) {
     const sigw_plan_desc& d = p->d;
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / d.L;
     const double V = d.L * d.L * d.L;
     const double dV = V / double(z.R3);
-    const void* ph = cplx_at(p->phi_hat, long(slot) * z.FS, z.cb);
+    const long s_stride = long(2) * z.stage * z.FS;
+    const long t_stride = long(3) * z.chunk * z.FS;
+    const long q_stride = long(12) * z.FS;
     for (int m = 0; m < 2; ++m) {
         void* Qm = cplx_at(p->Q, long(m) * 6 * z.FS, z.cb);
         for (int a0 = 0; a0 < d.n_alpha; a0 += z.chunk) {
             const int na = std::min(z.chunk, d.n_alpha - a0);
             sigw_status s;
-            // stage a few terms at a time: (W, Z) pairs small enough to stay in
-            // the last-level cache between gen_z and ypass3
+            // stage a few terms at a time: their (W, Z) pairs are expanded
+            // into gradient fields before the next group is generated
             for (int as = a0; as < a0 + na; as += z.stage) {
                 const int ns = std::min(z.stage, a0 + na - as);
                 void* Tdst = cplx_at(p->T, long(3) * (as - a0) * z.FS, z.cb);
                 s = timed(p, 0, [&] {
-                    p->eng->gen_z(ph, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V, p->Sst, p->stream);
+                    p->eng->gen_z(p->phi_hat, sel_dev, nb, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V,
+                                  p->Sst, s_stride, p->stream);
                 });
                 if (s) return s;
-                s = timed(p, 1, [&] { p->eng->ypass3(p->Sst, ns, Tdst, kF, p->stream); });
+                s = timed(p, 1, [&] { p->eng->ypass3(p->Sst, ns, nb, s_stride, Tdst, t_stride, kF, p->stream); });
                 if (s) return s;
             }
             s = timed(p, 2, [&] {
-                p->eng->xprod(p->T, p->sigma_tab[m], a0, na, dV, kF, Qm, n_planes, a0 > 0 ? 1 : 0, p->stream);
+                p->eng->xprod(p->T, t_stride, nb, p->sigma_tab[m], a0, na, dV, kF, Qm, q_stride, n_planes,
+                              a0 > 0 ? 1 : 0, p->stream);
             });
             if (s) return s;
         }
     }
-    return timed(p, 3, [&] { p->eng->ypass(p->Q, 12, z.FS, n_planes, -1, p->stream); });
+    return timed(p, 3, [&] { p->eng->ypass(p->Q, 12, z.FS, n_planes, -1, nb, q_stride, p->stream); });
+}
+
+// Stage a host slot list into the device slot list (pinned copy, no sync
+// unless the previous list's copy is still pending).
+sigw_status upload_sel(sigw_plan* p, const int* slots, int n) {
+    if (p->sel_inflight) {
+        HIP_TRY(p, hipEventSynchronize(p->sel_ev));
+        p->sel_inflight = false;
+    }
+    std::copy(slots, slots + n, p->h_sel);
+    HIP_TRY(p, hipMemcpyAsync(p->d_sel, p->h_sel, size_t(n) * 4, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipEventRecord(p->sel_ev, p->stream));
+    p->sel_inflight = true;
+    return SIGW_OK;
 }
 
 sigw_status check_launch(sigw_plan* p) {
@@ -413,14 +439,18 @@ sigw_status check_targets(sigw_plan* p, int n_k, const double* kt, const double*
     return SIGW_OK;
 }
 
-// Enqueue lut + convolutions + zbin + finalize of targets [0, n_k) for one
-// slot; sums/cnts land at device offset `out0`.  valid[b] = 0 marks an empty shell.
-sigw_status enqueue_spectrum(sigw_plan* p, int slot, int n_k, const double* kt, const double* lo,
-                             const double* hi, int out0, std::vector<int>& valid) {
+// Enqueue lut + convolutions + zbin + finalize of targets [0, n_k) for the
+// n_sel realisations in slots[]; realisation i's sums land at device offset
+// i * n_k + b.  Realisations run batch at a time.  valid[b] = 0 marks an
+// empty shell.
+sigw_status enqueue_spectrum(sigw_plan* p, const int* sel_dev, int n_sel, int n_k, const double* kt,
+                             const double* lo, const double* hi, double* sums, unsigned long long* cnts,
+                             std::vector<int>& valid) {
     const sigw_plan_desc& d = p->d;
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / d.L;
     valid.assign(n_k, 0);
+    const int zb = p->eng->zbin_blocks();
     for (int b = 0; b < n_k; ++b) {
         int n2_lo = 0, n2_hi = -1;
         if (!shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi)) continue;
@@ -428,14 +458,18 @@ sigw_status enqueue_spectrum(sigw_plan* p, int slot, int n_k, const double* kt, 
         const int kxm = std::min(d.N / 2, (int)std::floor(std::sqrt((double)n2_hi)));
         const int n_planes = kxm + 1;
         p->eng->lut(kF, kt[b], lo[b], hi[b], p->edges, d.n_modes, p->lut_u, p->lut_shell, p->stream);
-        sigw_status s = enqueue_convolutions(p, slot, kt[b], n_planes);
-        if (s) return s;
-        s = timed(p, 4, [&] {
-            p->eng->zbin(p->Q, p->lut_shell, n2_lo, n2_hi, p->part_sum, p->part_cnt, p->stream);
-        });
-        if (s) return s;
-        p->eng->finalize(p->part_sum, p->part_cnt, p->eng->zbin_blocks(), p->sums + out0 + b,
-                         p->cnts + out0 + b, p->stream);
+        for (int g0 = 0; g0 < n_sel; g0 += z.batch) {
+            const int nb = std::min(z.batch, n_sel - g0);
+            sigw_status s = enqueue_convolutions(p, sel_dev + g0, nb, kt[b], n_planes);
+            if (s) return s;
+            s = timed(p, 4, [&] {
+                p->eng->zbin(p->Q, nb, long(12) * z.FS, p->lut_shell, n2_lo, n2_hi, p->part_sum, p->part_cnt,
+                             p->stream);
+            });
+            if (s) return s;
+            p->eng->finalize(p->part_sum, p->part_cnt, zb, nb, sums + long(g0) * n_k + b,
+                             cnts + long(g0) * n_k + b, n_k, p->stream);
+        }
     }
     return check_launch(p);
 }
@@ -492,6 +526,7 @@ sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32
     d->A_p = 10.0;
     d->alpha_chunk = 0;
     d->scratch_terms = 0;
+    d->batch = 0;
     return SIGW_OK;
 }
 
@@ -522,11 +557,13 @@ sigw_status sigw_plan_destroy(sigw_plan_t p) {
     (void)hipStreamSynchronize(p->stream);
     void* bufs[] = {p->tw, p->edges, p->phi_tab[0], p->phi_tab[1], p->sigma_tab[0], p->sigma_tab[1],
                     p->lut_u, p->lut_shell, p->amp, p->phi_hat, p->T, p->Sst, p->Q, p->real, p->part_sum,
-                    p->part_cnt, p->sq_part, p->sums, p->cnts};
+                    p->part_cnt, p->sq_part, p->sums, p->cnts, p->d_sel};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_amp) (void)hipHostFree(p->h_amp);
     if (p->amp_ev) (void)hipEventDestroy(p->amp_ev);
+    if (p->h_sel) (void)hipHostFree(p->h_sel);
+    if (p->sel_ev) (void)hipEventDestroy(p->sel_ev);
     if (p->h_sums) (void)hipHostFree(p->h_sums);
     if (p->h_cnts) (void)hipHostFree(p->h_cnts);
     if (p->done_ev) (void)hipEventDestroy(p->done_ev);
@@ -571,7 +608,7 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
         }
         return true;
     };
-    const int zb_max = int(z.H * d->N);
+    const long zb_max = long(z.H * d->N) * z.batch;
     bool ok = alloc(&P->tw, size_t(d->N) * z.cb) && alloc((void**)&P->edges, (d->n_modes + 1) * 8) &&
               alloc(&P->phi_tab[0], size_t(d->n_modes) * d->n_alpha * z.rb) &&
               alloc(&P->phi_tab[1], size_t(d->n_modes) * d->n_alpha * z.rb) &&
@@ -579,8 +616,9 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
               alloc((void**)&P->lut_u, size_t(z.n2max + 1) * 2) && alloc((void**)&P->lut_shell, size_t(z.n2max + 1)) &&
               alloc((void**)&P->amp, size_t(z.n2max + 1) * 8) &&
               alloc(&P->phi_hat, size_t(d->n_slots) * z.FS * z.cb) &&
-              alloc(&P->T, size_t(3) * z.chunk * z.FS * z.cb) && alloc(&P->Sst, size_t(2) * z.stage * z.FS * z.cb) &&
-              alloc(&P->Q, size_t(12) * z.FS * z.cb) &&
+              alloc(&P->T, size_t(z.batch) * 3 * z.chunk * z.FS * z.cb) &&
+              alloc(&P->Sst, size_t(z.batch) * 2 * z.stage * z.FS * z.cb) &&
+              alloc(&P->Q, size_t(z.batch) * 12 * z.FS * z.cb) && alloc((void**)&P->d_sel, size_t(kMaxTargets) * 4) &&
               alloc(&P->real, size_t(z.R3) * z.rb) && alloc((void**)&P->part_sum, size_t(zb_max) * 8) &&
               alloc((void**)&P->part_cnt, size_t(zb_max) * 8) &&
               alloc((void**)&P->sq_part, size_t(kSumsqBlocks + 1) * 8) &&
@@ -592,6 +630,8 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
     if (hipHostMalloc((void**)&P->h_sums, kMaxTargets * 8) != hipSuccess ||
         hipHostMalloc((void**)&P->h_cnts, kMaxTargets * 8) != hipSuccess ||
         hipHostMalloc((void**)&P->h_amp, size_t(z.n2max + 1) * 8) != hipSuccess ||
+        hipHostMalloc((void**)&P->h_sel, size_t(kMaxTargets) * 4) != hipSuccess ||
+        hipEventCreate(&P->sel_ev) != hipSuccess ||
         hipEventCreate(&P->amp_ev) != hipSuccess || hipEventCreate(&P->done_ev) != hipSuccess) {
         sigw_plan_destroy(p.release());
         return SIGW_E_DEVICE;
@@ -647,7 +687,7 @@ sigw_status finish_field(sigw_plan* p, int slot, const sigw::MapParams& mp, bool
     p->eng->map_scale(p->real, p->real, p->sq_part + kSumsqBlocks, mp, (2.0 / 3.0) * dV, p->stream);
     void* dst = cplx_at(p->phi_hat, long(slot) * z.FS, z.cb);
     p->eng->xpass_r2c(p->real, dst, p->stream);
-    p->eng->ypass(dst, 1, z.FS, int(z.H), -1, p->stream);
+    p->eng->ypass(dst, 1, z.FS, int(z.H), -1, 1, 0, p->stream);
     p->eng->zpass(dst, z.H * p->d.N, -1, p->stream);
     sigw_status s = check_launch(p);
     if (s == SIGW_OK) p->has_field[slot] = 1;
@@ -693,11 +733,11 @@ sigw_status sigw_generate_field(sigw_plan_t p, int32_t slot, uint64_t seed, cons
     void* half = p->Q;   // scratch half spectrum
     p->eng->noise(seed, p->real, p->stream);
     p->eng->xpass_r2c(p->real, half, p->stream);
-    p->eng->ypass(half, 1, z.FS, int(z.H), -1, p->stream);
+    p->eng->ypass(half, 1, z.FS, int(z.H), -1, 1, 0, p->stream);
     p->eng->zpass(half, z.H * d.N, -1, p->stream);
     p->eng->filter(half, p->amp, p->stream);
     p->eng->zpass(half, z.H * d.N, +1, p->stream);
-    p->eng->ypass(half, 1, z.FS, int(z.H), +1, p->stream);
+    p->eng->ypass(half, 1, z.FS, int(z.H), +1, 1, 0, p->stream);
     p->eng->xpass_c2r(half, p->real, p->stream);
     sigw::MapParams m{mp->kind, mp->F_NL, mp->G_NL, mp->beta, mp->clip};
     return finish_field(p, slot, m, mp->kind == 1);
@@ -735,7 +775,8 @@ sigw_status sigw_source_convolutions(sigw_plan_t p, int32_t slot, double k_targe
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / p->d.L;
     p->eng->lut(kF, k_target, 0.0, 0.0, p->edges, p->d.n_modes, p->lut_u, p->lut_shell, p->stream);
-    if (sigw_status s = enqueue_convolutions(p, slot, k_target, int(z.H))) return s;
+    if (sigw_status s = upload_sel(p, &slot, 1)) return s;
+    if (sigw_status s = enqueue_convolutions(p, p->d_sel, 1, k_target, int(z.H))) return s;
     p->eng->zpass(p->Q, 12 * z.H * p->d.N, -1, p->stream);
     HIP_TRY(p, hipMemcpyAsync(qhat_dev, p->Q, size_t(12) * z.FS * z.cb, hipMemcpyDeviceToDevice, p->stream));
     return check_launch(p);
@@ -751,9 +792,8 @@ sigw_status sigw_spectrum_batch(sigw_plan_t p, int32_t n_sel, const int32_t* slo
     for (int i = 0; i < n_sel; ++i)
         if (sigw_status s = check_slot(p, slots[i], true)) return s;
     std::vector<int> valid;
-    for (int i = 0; i < n_sel; ++i) {
-        if (sigw_status s = enqueue_spectrum(p, slots[i], n_k, kt, lo, hi, i * n_k, valid)) return s;
-    }
+    if (sigw_status s = upload_sel(p, slots, n_sel)) return s;
+    if (sigw_status s = enqueue_spectrum(p, p->d_sel, n_sel, n_k, kt, lo, hi, p->sums, p->cnts, valid)) return s;
     const size_t cnt = size_t(n_sel) * n_k;
     if (cnt) {
         HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, cnt * 8, hipMemcpyDeviceToHost, p->stream));
@@ -781,7 +821,8 @@ sigw_status sigw_spectrum_enqueue(sigw_plan_t p, int32_t slot, int32_t n_k, cons
     if (n_k > 64) return fail(p, SIGW_E_INVALID, "asynchronous spectra take at most 64 targets");
     if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
     if (sigw_status s = check_slot(p, slot, true)) return s;
-    if (sigw_status s = enqueue_spectrum(p, slot, n_k, kt, lo, hi, 0, p->pend_valid)) return s;
+    if (sigw_status s = upload_sel(p, &slot, 1)) return s;
+    if (sigw_status s = enqueue_spectrum(p, p->d_sel, 1, n_k, kt, lo, hi, p->sums, p->cnts, p->pend_valid)) return s;
     if (n_k) {
         HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
         HIP_TRY(p, hipMemcpyAsync(p->h_cnts, p->cnts, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
@@ -807,6 +848,128 @@ sigw_status sigw_spectrum_poll(sigw_plan_t p, double* omega, int64_t* nmodes) {
     }
     const int n_k = int(p->pend_targets.size());
     to_omega(p, n_k, p->pend_targets.data(), p->h_sums, p->h_cnts, p->pend_valid.data(), omega, nmodes);
+    return SIGW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Captured spectra: the whole enqueue sequence of one batched spectrum as a
+// HIP graph, replayed for new fields in the same slots.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct sigw_graph {
+    sigw_plan* p = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    int n_sel = 0, n_k = 0;
+    std::vector<double> kt;
+    std::vector<int> valid;
+    int* d_slots = nullptr;
+    double* d_sums = nullptr;
+    unsigned long long* d_cnts = nullptr;
+    double* h_sums = nullptr;
+    unsigned long long* h_cnts = nullptr;
+    bool launched = false;
+};
+
+extern "C" {
+
+sigw_status sigw_graph_destroy(sigw_graph_t gr) {
+    if (!gr) return SIGW_E_INVALID;
+    if (gr->p) (void)hipStreamSynchronize(gr->p->stream);
+    if (gr->ge) (void)hipGraphExecDestroy(gr->ge);
+    if (gr->g) (void)hipGraphDestroy(gr->g);
+    if (gr->d_slots) (void)hipFree(gr->d_slots);
+    if (gr->d_sums) (void)hipFree(gr->d_sums);
+    if (gr->d_cnts) (void)hipFree(gr->d_cnts);
+    if (gr->h_sums) (void)hipHostFree(gr->h_sums);
+    if (gr->h_cnts) (void)hipHostFree(gr->h_cnts);
+    delete gr;
+    return SIGW_OK;
+}
+
+sigw_status sigw_graph_create(sigw_plan_t p, int32_t n_sel, const int32_t* slots, int32_t n_k, const double* kt,
+                              const double* lo, const double* hi, sigw_graph_t* out) {
+    if (!p || !out) return SIGW_E_INVALID;
+    *out = nullptr;
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    if (p->timing) return fail(p, SIGW_E_STATE, "disable timing before capturing a graph");
+    if (n_sel < 1 || !slots) return fail(p, SIGW_E_INVALID, "need at least one slot");
+    if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
+    if (n_k < 1) return fail(p, SIGW_E_INVALID, "need at least one target");
+    if (long(n_sel) * n_k > kMaxTargets) return fail(p, SIGW_E_INVALID, "n_sel * n_k exceeds 4096");
+    for (int i = 0; i < n_sel; ++i)
+        if (slots[i] < 0 || slots[i] >= p->d.n_slots) return fail(p, SIGW_E_INVALID, "slot out of range");
+    std::unique_ptr<sigw_graph> gr(new (std::nothrow) sigw_graph());
+    if (!gr) return SIGW_E_NOMEM;
+    gr->p = p;
+    gr->n_sel = n_sel;
+    gr->n_k = n_k;
+    gr->kt.assign(kt, kt + n_k);
+    const size_t cnt = size_t(n_sel) * n_k;
+    if (hipMalloc((void**)&gr->d_slots, size_t(n_sel) * 4) != hipSuccess ||
+        hipMalloc((void**)&gr->d_sums, cnt * 8) != hipSuccess || hipMalloc((void**)&gr->d_cnts, cnt * 8) != hipSuccess ||
+        hipHostMalloc((void**)&gr->h_sums, cnt * 8) != hipSuccess ||
+        hipHostMalloc((void**)&gr->h_cnts, cnt * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_NOMEM, "graph buffers");
+    }
+    // the slot list is part of the graph's inputs, staged before capture
+    if (hipMemcpy(gr->d_slots, slots, size_t(n_sel) * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_DEVICE, "graph slot list upload");
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_DEVICE, "hipStreamSynchronize before capture");
+    }
+    if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_DEVICE, "hipStreamBeginCapture (a graph needs a non-null plan stream)");
+    }
+    sigw_status s = enqueue_spectrum(p, gr->d_slots, n_sel, n_k, kt, lo, hi, gr->d_sums, gr->d_cnts, gr->valid);
+    if (s == SIGW_OK) {
+        if (hipMemcpyAsync(gr->h_sums, gr->d_sums, cnt * 8, hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+            hipMemcpyAsync(gr->h_cnts, gr->d_cnts, cnt * 8, hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+            s = fail(p, SIGW_E_DEVICE, "result copies during capture");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->stream, &g);
+    gr->g = g;
+    if (s != SIGW_OK) {
+        sigw_graph_destroy(gr.release());
+        return s;
+    }
+    if (ec != hipSuccess || !g) {
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    }
+    if (hipGraphInstantiate(&gr->ge, gr->g, nullptr, nullptr, 0) != hipSuccess) {
+        sigw_graph_destroy(gr.release());
+        return fail(p, SIGW_E_DEVICE, "hipGraphInstantiate");
+    }
+    *out = gr.release();
+    return SIGW_OK;
+}
+
+sigw_status sigw_graph_launch(sigw_graph_t gr) {
+    if (!gr) return SIGW_E_INVALID;
+    sigw_plan* p = gr->p;
+    HIP_TRY(p, hipGraphLaunch(gr->ge, p->stream));
+    gr->launched = true;
+    return SIGW_OK;
+}
+
+sigw_status sigw_graph_results(sigw_graph_t gr, double* omega, int64_t* nmodes) {
+    if (!gr) return SIGW_E_INVALID;
+    sigw_plan* p = gr->p;
+    if (!gr->launched) return fail(p, SIGW_E_STATE, "graph not launched");
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (int i = 0; i < gr->n_sel; ++i)
+        to_omega(p, gr->n_k, gr->kt.data(), gr->h_sums + size_t(i) * gr->n_k, gr->h_cnts + size_t(i) * gr->n_k,
+                 gr->valid.data(), omega ? omega + size_t(i) * gr->n_k : nullptr,
+                 nmodes ? nmodes + size_t(i) * gr->n_k : nullptr);
     return SIGW_OK;
 }
 

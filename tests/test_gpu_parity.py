@@ -220,3 +220,18 @@ def test_batch_async_chunking_and_determinism(tabs):
         chunked = pl.spectrum(0, t, lo, hi)[0]
     ok = alone[1] > 0
     np.testing.assert_allclose(chunked[ok], alone[1][ok], rtol=2e-5)
+    # several realisations per launch (groups of 2 over 3 slots: one ragged
+    # group) give the same bits as one realisation per launch
+    with P.Plan(N, prec="f32", n_slots=3, batch=2) as pl:
+        for s in range(3):
+            pl.generate_field(s, 10 + s, spec, W.NGMap("local", F_NL=float(s)))
+        batched, _ = pl.spectrum_batch([0, 1, 2], t, lo, hi)
+        staged, _ = pl.spectrum_batch([1], t, lo, hi)
+    for s in range(3):
+        np.testing.assert_array_equal(batched[s], alone[s])
+    np.testing.assert_array_equal(staged[0], alone[1])
+    # staging one term at a time through the (W, Z) scratch changes nothing
+    with P.Plan(N, prec="f32", scratch_terms=1) as pl:
+        pl.generate_field(0, 11, spec, W.NGMap("local", F_NL=1.0))
+        one = pl.spectrum(0, t, lo, hi)[0]
+    np.testing.assert_array_equal(one, alone[1])
