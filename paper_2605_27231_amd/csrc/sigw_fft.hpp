@@ -1,13 +1,8 @@
 // Device-side FFT building blocks for gfx950: complex arithmetic, radix-2/3/4/8
-// butterflies and a Stockham autosort pass sequence that runs NL independent
-// lines of length N held in LDS, with NT threads of the workgroup.
-//
-// Stockham step (radix r, L = product of the radices already applied):
-//   for j in [0, N/r):  k = j mod L
-//     a_m = x[j + m N/r] * w^(m k),  w = exp(sign 2 pi i / (L r)),  m = 0..r-1
-//     b_p = sum_m a_m exp(sign 2 pi i m p / r)
-//     y[(j - k) r + k + p L] = b_p
-// After all steps the output is in natural order.  The forward transform uses
+// butterflies, register DFTs of composite size with compile-time twiddles,
+// and the two-phase line transform (register DFT, LDS transpose, register
+// DFT) that every pass of the pipeline is built from.  Sign convention:
+// out[p] = sum_m a[m] exp(sign 2 pi i m p / r); the forward transform uses
 // sign = -1, the inverse sign = +1 (unnormalised).
 #pragma once
 
@@ -98,97 +93,61 @@ template <int R_, int SIGN, typename C> __device__ __forceinline__ void dft(C* a
     else static_assert(R_ == 2, "unsupported radix");
 }
 
-// ---- radix schedules (product = N) ----
-template <int N> struct Radices;
-template <> struct Radices<8> { static constexpr int n = 1; static constexpr int r[1] = {8}; };
-template <> struct Radices<16> { static constexpr int n = 2; static constexpr int r[2] = {4, 4}; };
-template <> struct Radices<32> { static constexpr int n = 2; static constexpr int r[2] = {8, 4}; };
-template <> struct Radices<64> { static constexpr int n = 2; static constexpr int r[2] = {8, 8}; };
-template <> struct Radices<128> { static constexpr int n = 3; static constexpr int r[3] = {8, 4, 4}; };
-template <> struct Radices<256> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 4}; };
-template <> struct Radices<384> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 2, 3}; };
-template <> struct Radices<512> { static constexpr int n = 3; static constexpr int r[3] = {8, 8, 8}; };
-
-// One Stockham step over NL lines; line l, element e lives at buf[l*LS + e*ES].
-// tw[t] = exp(-2 pi i t / N), t = 0..N-1.
-template <typename C, int N, int RD, int L, int NL, int NT, int SIGN, int LS, int ES>
-__device__ __forceinline__ void stockham_step(C* buf, const C* __restrict__ tw, int tid) {
-    constexpr int M = N / RD;
-    constexpr int NB = NL * M;
-    constexpr int PER = (NB + NT - 1) / NT;
-    C v[PER][RD];
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * NT;
-        if ((NB % NT == 0) || b < NB) {
-            const int line = b / M;
-            const int j = b - line * M;
-#pragma unroll
-            for (int m = 0; m < RD; ++m) v[p][m] = buf[line * LS + (j + m * M) * ES];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * NT;
-        if ((NB % NT == 0) || b < NB) {
-            const int line = b / M;
-            const int j = b - line * M;
-            const int k = j % L;
-            if constexpr (L > 1) {
-#pragma unroll
-                for (int m = 1; m < RD; ++m) {
-                    C w = tw[(m * k) * (N / (L * RD))];
-                    if (SIGN > 0) w.y = -w.y;
-                    v[p][m] = cmul(v[p][m], w);
-                }
-            }
-            dft<RD, SIGN>(v[p]);
-            const int base = (j - k) * RD + k;
-#pragma unroll
-            for (int m = 0; m < RD; ++m) buf[line * LS + (base + m * L) * ES] = v[p][m];
-        }
-    }
-    __syncthreads();
-}
-
-template <typename C, int N, int NL, int NT, int SIGN, int LS, int ES, int S, int L>
-__device__ __forceinline__ void stockham_from(C* buf, const C* __restrict__ tw, int tid) {
-    if constexpr (S < Radices<N>::n) {
-        constexpr int RD = Radices<N>::r[S];
-        stockham_step<C, N, RD, L, NL, NT, SIGN, LS, ES>(buf, tw, tid);
-        stockham_from<C, N, NL, NT, SIGN, LS, ES, S + 1, L * RD>(buf, tw, tid);
-    }
-}
-
-// Full length-N transform of NL lines in LDS.  The caller has synchronised
-// after filling buf; on return every thread may read the result.
-template <typename C, int N, int NL, int NT, int SIGN, int LS, int ES>
-__device__ __forceinline__ void lds_fft(C* buf, const C* __restrict__ tw, int tid) {
-    stockham_from<C, N, NL, NT, SIGN, LS, ES, 0, 1>(buf, tw, tid);
-}
-
-
 // ----------------------------------------------------------------------------
-// Register DFTs of composite size (four-step inside one thread).
-// Twiddles come from the length-N table tw[t] = exp(-2 pi i t / N) at
-// compile-time offsets, so they are uniform (scalar) loads.
+// Register DFTs of composite size (four-step inside one thread).  Their
+// twiddles are exp(sign 2 pi i m / R) with R dividing 96 and m fixed once the
+// loops are unrolled, so they are immediate constants, and the trivial ones
+// (1, -1, +-i) cost no multiplication.
 // ----------------------------------------------------------------------------
+// cos(2 pi m / 96) for m = 0..24, correctly rounded
+__device__ constexpr double kCos96[25] = {
+    1.0, 0.99785892323860350673807, 0.991444861373810411144558,
+    0.980785280403230449126182, 0.965925826289068286749743, 0.946930129495105664255804,
+    0.923879532511286756128183, 0.896872741532688303894104, 0.866025403784438646763723,
+    0.831469612302545237078788, 0.793353340291235164579777, 0.751839807478977396407519,
+    0.707106781186547524400844, 0.659345815100068868425125, 0.608761429008720639416098,
+    0.555570233019602224742831, 0.5, 0.442288690219001281995239,
+    0.38268343236508977172846, 0.321439465303161580701058, 0.258819045102520762348899,
+    0.195090322016128267848285, 0.130526192220051591548406, 0.065403129230143066815316,
+    0.0,
+};
+
+__device__ constexpr double cos96(int e) {
+    e = ((e % 96) + 96) % 96;
+    return e <= 24 ? kCos96[e] : e <= 48 ? -kCos96[48 - e] : e <= 72 ? -kCos96[e - 48] : kCos96[96 - e];
+}
+
+// a * exp(sign 2 pi i m / R); m is a constant after unrolling, so the
+// branches fold away
+template <int SIGN, int R, typename C> __device__ __forceinline__ C ctw_mul(C a, int m) {
+    static_assert(96 % R == 0, "register DFT twiddles are multiples of 2 pi / 96");
+    using T = decltype(C::x);
+    const int e = (m % R) * (96 / R);
+    if (e == 0) return a;
+    if (e == 48) return cmk<C>(-a.x, -a.y);
+    if (e == 24) return mul_si<SIGN>(a);
+    if (e == 72) return mul_si<-SIGN>(a);
+    const T c = T(cos96(e)), s = T(SIGN) * T(cos96(e - 24));
+    return cmk<C>(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
 template <int R> struct RegSplit;                 // R = F * G, F a base radix
 template <> struct RegSplit<12> { static constexpr int F = 4, G = 3; };
 template <> struct RegSplit<16> { static constexpr int F = 4, G = 4; };
 template <> struct RegSplit<24> { static constexpr int F = 8, G = 3; };
 template <> struct RegSplit<32> { static constexpr int F = 8, G = 4; };
 
+// Inter-phase twiddle exp(sign 2 pi i e / N) from the table tw[t] =
+// exp(-2 pi i t / N) (in global memory or an LDS copy).
 template <int SIGN, int N, typename C>
-__device__ __forceinline__ C tw_at(const C* __restrict__ tw, int e) {
+__device__ __forceinline__ C tw_at(const C* tw, int e) {
     C w = tw[e];
     if (SIGN > 0) w.y = -w.y;
     return w;
 }
 
-template <int R, int SIGN, int N, typename C>
-__device__ __forceinline__ void reg_dft(C* a, const C* __restrict__ tw) {
+template <int R, int SIGN, typename C>
+__device__ __forceinline__ void reg_dft(C* a) {
     if constexpr (R == 1) {
     } else if constexpr (R == 2 || R == 3 || R == 4 || R == 8) {
         dft<R, SIGN>(a);
@@ -196,7 +155,6 @@ __device__ __forceinline__ void reg_dft(C* a, const C* __restrict__ tw) {
         constexpr int F = RegSplit<R>::F;
         constexpr int G = RegSplit<R>::G;
         static_assert(F * G == R, "bad split");
-        static_assert(N % R == 0, "register DFT size must divide N");
         C tmp[R];
         // x index n = g + G f; out index k = kf + F kg
 #pragma unroll
@@ -206,17 +164,14 @@ __device__ __forceinline__ void reg_dft(C* a, const C* __restrict__ tw) {
             for (int f = 0; f < F; ++f) v[f] = a[g + G * f];
             dft<F, SIGN>(v);
 #pragma unroll
-            for (int kf = 0; kf < F; ++kf) {
-                if (g * kf == 0) tmp[g * F + kf] = v[kf];
-                else tmp[g * F + kf] = cmul(v[kf], tw_at<SIGN, N>(tw, ((g * kf) % R) * (N / R)));
-            }
+            for (int kf = 0; kf < F; ++kf) tmp[g * F + kf] = ctw_mul<SIGN, R>(v[kf], g * kf);
         }
 #pragma unroll
         for (int kf = 0; kf < F; ++kf) {
             C w[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) w[g] = tmp[g * F + kf];
-            reg_dft<G, SIGN, N>(w, tw);
+            reg_dft<G, SIGN>(w);
 #pragma unroll
             for (int kg = 0; kg < G; ++kg) a[kf + F * kg] = w[kg];
         }
@@ -262,12 +217,27 @@ template <int N, int NL, bool LINE_FAST> struct TPLayout {
     }
 };
 
-// Phase 1.  tw serves the register DFT's own twiddles (fixed indices, read
-// through the scalar cache); twv serves the inter-phase twiddles
-// tw[t k1], whose index depends on the lane: a copy of the table in LDS
-// keeps those off the vector memory path.
+// Phase 1 of one item whose inputs are already in registers: a[m] holds
+// element t + R2 m of line `line`; a is overwritten.  The inter-phase
+// twiddles tw[t k1] depend on the lane: with tw a copy of the table in LDS
+// they stay off the vector memory path.
+template <typename C, int N, int SIGN, int NL, bool LINE_FAST>
+__device__ __forceinline__ void tp_phase1_item(C* a, int line, int t, C* lds, const C* tw) {
+    using Lay = TPLayout<N, NL, LINE_FAST>;
+    constexpr int R1 = Lay::R1;
+    reg_dft<R1, SIGN>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        C v = a[k1];
+        if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(tw, t * k1));
+        lds[Lay::at(line, k1, t)] = v;
+    }
+}
+
+// Phase 1 over all NL lines, items spread over NT threads; ld(line, n)
+// returns element n of a line.
 template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
-__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, const C* twv, int tid) {
+__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* tw, int tid) {
     using Lay = TPLayout<N, NL, LINE_FAST>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = NL * R2;
@@ -280,20 +250,9 @@ __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__
             C a[R1];
 #pragma unroll
             for (int m = 0; m < R1; ++m) a[m] = ld(line, t + R2 * m);
-            reg_dft<R1, SIGN, N>(a, tw);
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                C v = a[k1];
-                if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(twv, t * k1));
-                lds[Lay::at(line, k1, t)] = v;
-            }
+            tp_phase1_item<C, N, SIGN, NL, LINE_FAST>(a, line, t, lds, tw);
         }
     }
-}
-
-template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
-__device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* __restrict__ tw, int tid) {
-    tp_phase1<C, N, SIGN, NL, NT, LINE_FAST>(ld, lds, tw, tw, tid);
 }
 
 // Copy of the N-entry twiddle table into LDS, for the lane-dependent twiddles
@@ -305,7 +264,7 @@ __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw,
 }
 
 template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class ST>
-__device__ __forceinline__ void tp_phase2(ST&& st, const C* lds, const C* __restrict__ tw, int tid) {
+__device__ __forceinline__ void tp_phase2(ST&& st, const C* lds, int tid) {
     using Lay = TPLayout<N, NL, LINE_FAST>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = NL * R1;
@@ -318,7 +277,7 @@ __device__ __forceinline__ void tp_phase2(ST&& st, const C* lds, const C* __rest
             C b[R2];
 #pragma unroll
             for (int t = 0; t < R2; ++t) b[t] = lds[Lay::at(line, k1, t)];
-            reg_dft<R2, SIGN, N>(b, tw);
+            reg_dft<R2, SIGN>(b);
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) st(line, k1 + R1 * k2, b[k2]);
         }
@@ -335,7 +294,7 @@ struct TPRegs {
     static constexpr int ITEMS = NL * R1;
     static constexpr int PER = (ITEMS + NT - 1) / NT;
     C v[PER][R2];
-    __device__ __forceinline__ void run(const C* lds, const C* __restrict__ tw, int tid) {
+    __device__ __forceinline__ void run(const C* lds, int tid) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int w = tid + i * NT;
@@ -344,7 +303,7 @@ struct TPRegs {
                 const int k1 = LINE_FAST ? w / NL : w % R1;
 #pragma unroll
                 for (int t = 0; t < R2; ++t) v[i][t] = lds[Lay::at(line, k1, t)];
-                reg_dft<R2, SIGN, N>(v[i], tw);
+                reg_dft<R2, SIGN>(v[i]);
             }
         }
     }

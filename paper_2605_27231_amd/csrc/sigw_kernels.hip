@@ -53,6 +53,18 @@ template <typename R, int N> struct Shape {
 
 __device__ __forceinline__ int signed_index(int i, int N) { return i < N / 2 ? i : i - N; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  xcd_block renumbers the nb blocks of a grid row so that
+// every XCD works through one contiguous range of logical blocks.  The
+// x-pass tiles read half cache lines (64 bytes) whose other halves belong to
+// the neighbouring z chunk: in this order both halves are requested through
+// the same L2 instead of being fetched from HBM twice.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % 8, s = b / 8;
+    const int q = nb / 8, r = nb % 8;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // ----------------------------------------------------------------------------
 // White noise: Philox4x64-10 (Salmon et al., SC'11) + Box-Muller cosine branch.
 // The binary64 ln and cos below follow an explicit operation sequence with no
@@ -226,7 +238,7 @@ __global__ __launch_bounds__(256) void k_zpass(typename CplxOf<R>::T* __restrict
     };
     tp_phase1<C, N, SIGN, RB, NT, false>(ld, lds, tw, tid);
     __syncthreads();
-    tp_phase2<C, N, SIGN, RB, NT, false>(st, lds, tw, tid);
+    tp_phase2<C, N, SIGN, RB, NT, false>(st, lds, tid);
 }
 
 // y pass: complex DFT along y of tiles (field, kx plane, z chunk), in place.
@@ -255,7 +267,7 @@ __global__ __launch_bounds__(256) void k_ypass(typename CplxOf<R>::T* __restrict
     auto st = [&](int zz, int y, C v) { base[long(y) * N + zz] = v; };
     tp_phase1<C, N, SIGN, TZ, NT, true>(ld, lds, tw, tid);
     __syncthreads();
-    tp_phase2<C, N, SIGN, TZ, NT, true>(st, lds, tw, tid);
+    tp_phase2<C, N, SIGN, TZ, NT, true>(st, lds, tid);
 }
 
 // x pass, real -> half (forward).  Tile (y, z chunk); the z pairs (2p, 2p+1)
@@ -279,15 +291,16 @@ __global__ __launch_bounds__(256) void k_xpass_r2c(const R* __restrict__ in, typ
     __shared__ C lds[TPLayout<N, P, true>::size];
     __shared__ C zb[P * LS];
     const int tid = threadIdx.x;
-    const int zc = blockIdx.x % NZC;
-    const int y = blockIdx.x / NZC;
+    const int bl = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int zc = bl % NZC;
+    const int y = bl / NZC;
     const int z0 = zc * TZ;
     const C* inc = reinterpret_cast<const C*>(in);
     auto ld = [&](int p, int x) -> C { return inc[((long(x) * N + y) * N + z0) / 2 + p]; };
     auto st = [&](int p, int k, C v) { zb[p * LS + k] = v; };
     tp_phase1<C, N, -1, P, NT, true>(ld, lds, tw, tid);
     __syncthreads();
-    tp_phase2<C, N, -1, P, NT, true>(st, lds, tw, tid);
+    tp_phase2<C, N, -1, P, NT, true>(st, lds, tid);
     __syncthreads();
     for (int e = tid; e < H * P; e += NT) {
         const int k = e / P, p = e % P;
@@ -335,8 +348,9 @@ __global__ __launch_bounds__(256) void k_xpass_c2r(const typename CplxOf<R>::T* 
     constexpr int NZC = N / TZ;
     __shared__ C lds[TPLayout<N, P, true>::size];
     const int tid = threadIdx.x;
-    const int zc = blockIdx.x % NZC;
-    const int y = blockIdx.x / NZC;
+    const int bl = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int zc = bl % NZC;
+    const int y = bl / NZC;
     const int z0 = zc * TZ;
     C* outc = reinterpret_cast<C*>(out);
     const C* col0 = in + long(y) * N + z0;
@@ -344,7 +358,7 @@ __global__ __launch_bounds__(256) void k_xpass_c2r(const typename CplxOf<R>::T* 
     auto st = [&](int p, int x, C v) { outc[((long(x) * N + y) * N + z0) / 2 + p] = v; };
     tp_phase1<C, N, +1, P, NT, true>(ld, lds, tw, tid);
     __syncthreads();
-    tp_phase2<C, N, +1, P, NT, true>(st, lds, tw, tid);
+    tp_phase2<C, N, +1, P, NT, true>(st, lds, tid);
 }
 
 // ----------------------------------------------------------------------------
@@ -526,7 +540,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
                             f[m] = cmk<C>(-q * v[m].y, q * v[m].x);   // i q_z v
                         }
                     }
-                    reg_dft<R1, +1, N>(f, tw);
+                    reg_dft<R1, +1>(f);
 #pragma unroll
                     for (int k1 = 0; k1 < R1; ++k1) {
                         C o = f[k1];
@@ -542,7 +556,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
             const int j = line / RB, row = line % RB;
             T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
         };
-        tp_phase2<C, N, +1, NL, NT, false>(st, lds, tw, tid);
+        tp_phase2<C, N, +1, NL, NT, false>(st, lds, tid);
         __syncthreads();
     }
 }
@@ -566,12 +580,18 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     constexpr int NZC = N / TZ;
     constexpr int H = N / 2 + 1;
     constexpr long FS = Shape<R, N>::FS;
-    __shared__ C lds[TPLayout<N, TZ, true>::size];
+    using Lay = TPLayout<N, TZ, true>;
+    constexpr int R1 = Lay::R1, R2 = Lay::R2;
+    constexpr int ITEMS = TZ * R2;
+    constexpr int PER = (ITEMS + NT - 1) / NT;
+    __shared__ C lds[Lay::size];
     __shared__ C twl[N];
     const int tid = threadIdx.x;
     stage_twiddles<C, N, NT>(twl, tw, tid);
-    __syncthreads();
-    const long b = blockIdx.x;
+    // consecutive z chunks of a (term, kx) plane share an XCD and its L2,
+    // which keeps the DRAM pages of that plane's rows together (measured
+    // faster)
+    const long b = xcd_block(int(blockIdx.x), int(gridDim.x));
     const int zc = int(b % NZC);
     const long fp = b / NZC;
     const int kx = int(fp % H);
@@ -582,26 +602,62 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     const C* w = S + 2 * al * FS + off;
     const C* z = w + FS;
     const R qx = (kx == N / 2) ? R(0) : k_F * R(kx);     // qt_x of this plane
+    // the W tile feeds U_x and U_y: with one phase-1 item per thread it is
+    // read once, into registers (line tid % TZ, elements tid / TZ + R2 m);
+    // with more, registers are too scarce and U_y reads it again
+    constexpr bool KEEP = PER == 1;
+    C wr[1][R1];
+    if constexpr (KEEP) {
+        const int it = tid;
+        const bool ok = (ITEMS % NT == 0) || it < ITEMS;
+        const int line = it % TZ, t = it / TZ;
+#pragma unroll
+        for (int m = 0; m < R1; ++m) wr[0][m] = ok ? w[long(t + R2 * m) * N + line] : cmk<C>(R(0), R(0));
+    }
+    __syncthreads();                                        // twl
 #pragma unroll 1
     for (int j = 0; j < 3; ++j) {
-        const C* src = j == 2 ? z : w;
-        C* dst = T + (3 * al + j) * FS + off;
-        auto ld = [&](int zz, int y) -> C {
-            C v = src[long(y) * N + zz];
-            if (j < 2) {
-                R q = qx;
-                if (j == 1) {
-                    const int ny = signed_index(y, N);
-                    q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+        if constexpr (KEEP) {
+            const int it = tid;
+            if ((ITEMS % NT == 0) || it < ITEMS) {
+                const int line = it % TZ, t = it / TZ;
+                C v[R1];
+#pragma unroll
+                for (int m = 0; m < R1; ++m) {
+                    const int yy = t + R2 * m;
+                    if (j == 2) {
+                        v[m] = z[long(yy) * N + line];
+                    } else {
+                        R q = qx;
+                        if (j == 1) {
+                            const int ny = signed_index(yy, N);
+                            q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+                        }
+                        v[m] = cmk<C>(-q * wr[0][m].y, q * wr[0][m].x);
+                    }
                 }
-                v = cmk<C>(-q * v.y, q * v.x);
+                tp_phase1_item<C, N, +1, TZ, true>(v, line, t, lds, twl);
             }
-            return v;
-        };
-        auto st = [&](int zz, int y, C v) { dst[long(y) * N + zz] = v; };
-        tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, tw, twl, tid);
+        } else {
+            const C* src = j == 2 ? z : w;
+            auto ld = [&](int zz, int yy) -> C {
+                C v = src[long(yy) * N + zz];
+                if (j < 2) {
+                    R q = qx;
+                    if (j == 1) {
+                        const int ny = signed_index(yy, N);
+                        q = (ny == -N / 2) ? R(0) : k_F * R(ny);
+                    }
+                    v = cmk<C>(-q * v.y, q * v.x);
+                }
+                return v;
+            };
+            tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, twl, tid);
+        }
         __syncthreads();
-        tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tw, tid);
+        C* dst = T + (3 * al + j) * FS + off;
+        auto st = [&](int zz, int y, C v) { dst[long(y) * N + zz] = v; };
+        tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tid);
         __syncthreads();
     }
 }
@@ -644,8 +700,9 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
     __shared__ C twl[N];
     const int tid = threadIdx.x;
     stage_twiddles<C, N, NT>(twl, tw, tid);
-    const int zc = blockIdx.x % NZC;
-    const int y = blockIdx.x / NZC;
+    const int bl = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int zc = bl % NZC;
+    const int y = bl / NZC;
     const int z0 = zc * TZ;
     const C* T = T_all + blockIdx.y * t_stride;
     C* Qx = Q_all + blockIdx.y * q_stride;
@@ -729,7 +786,7 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
                     }
                     v[m] = m < R1 / 2 ? cmk<C>(a.x - b.y, a.y + b.x) : cmk<C>(a.x + b.y, b.x - a.y);
                 }
-                reg_dft<R1, +1, N>(v, tw);
+                reg_dft<R1, +1>(v);
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
                     C o = v[k1];
@@ -755,7 +812,7 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
         // after every tile load in flight.
         if (a + 1 < a0 + na) issue_tile(a + 1, raw[cur ^ 1]);
         TPRegs<C, N, +1, NLI, NT, true> g;
-        g.run(Z, tw, tid);
+        g.run(Z, tid);
         __syncthreads();
         g.store([&](int line, int x, C v) { Z[line * LS + x] = v; }, tid);
         __syncthreads();
@@ -792,10 +849,10 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
             zq[(qq / N) * LS + (qq % N)] = Q[c][i];
         }
         __syncthreads();
-        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, tw, twl, tid);
+        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, twl, tid);
         __syncthreads();
         TPRegs<C, N, -1, P, NT, false> f;
-        f.run(zt, tw, tid);
+        f.run(zt, tid);
         f.store([&](int p, int k, C v) { zq[p * LS + k] = v; }, tid);
         __syncthreads();
         for (int e = tid; e < H * P; e += NT) {
@@ -902,7 +959,7 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
         tp_phase1<C, N, -1, NL, NT, false>(ld, buf, tw, tid);
         __syncthreads();
         TPRegs<C, N, -1, NL, NT, false> f;
-        f.run(buf, tw, tid);
+        f.run(buf, tid);
         __syncthreads();
         f.store([&](int line, int kz, C v) { buf[line * LS + kz] = v; }, tid);
         __syncthreads();
