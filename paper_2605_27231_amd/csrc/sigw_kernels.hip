@@ -669,13 +669,16 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
 //
 // Per term the raw tile (3 fields x (N/2+1) kx x TZX z values) is loaded
 // once, coalesced, straight from global memory into LDS by the gfx950
-// global-to-LDS loads (no registers involved), double buffered: the tile of
-// term a+1 is in flight while term a is transformed and multiplied.  The
-// Hermitian extension of the x lines is applied when phase 1 reads the tile
-// back (the gradient factors were applied by the earlier passes).
+// global-to-LDS loads (no registers involved).  The tile of term a+1 is
+// requested as soon as phase 1 of term a has read the buffer, so it is in
+// flight during phase 2 and the products; one buffer per block keeps the
+// LDS at about 52 KB, three blocks per CU, which hides more latency than a
+// second buffer would (measured).  The Hermitian extension of the x lines
+// is applied when phase 1 reads the tile back (the gradient factors were
+// applied by the earlier passes).
 // ----------------------------------------------------------------------------
 template <typename R, int N>
-__global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
+__global__ __launch_bounds__(256, 3) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
                                                   const R* __restrict__ sigma, int a0, int na, R dV, R k_F,
                                                   typename CplxOf<R>::T* __restrict__ Q_all, long q_stride,
                                                   int n_planes, int accumulate,
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
     constexpr int NLI = 3 * P;                                   // inverse lines (field, z pair)
     constexpr int NRAW = 3 * H * P;                              // raw pairs per term
     constexpr int TRS = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
-    __shared__ C raw[2][2 * NRAW];                               // [buffer][field][kx][pair][2]
+    __shared__ C raw[2 * NRAW];                                  // [field][kx][pair][2]
     __shared__ C Z[TRS];                                         // transpose, then G lines
     __shared__ C twl[N];
     const int tid = threadIdx.x;
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
             }
         }
     };
-    const C* rawc = raw[0];
+    const C* rawc = raw;
     using LayI = TPLayout<N, NLI, true>;
     constexpr int R1 = LayI::R1, R2 = LayI::R2;
     constexpr int ITEMS1 = NLI * R2;
@@ -797,20 +800,17 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
         }
     };
 
-    issue_tile(a0, raw[0]);
+    issue_tile(a0, raw);
     for (int a = a0; a < a0 + na; ++a) {
-        const int cur = (a - a0) & 1;
         __builtin_amdgcn_s_waitcnt(0);    // this wavefront's loads of tile a have landed
         __syncthreads();                  // ... and every wavefront's; Z is free again
-        rawc = raw[cur];
+        rawc = raw;
         phase1();
         __syncthreads();
-        // the next tile is requested after phase 1, so that its LDS writes
-        // overlap phase 2 and the products rather than phase 1's tile reads
-        // (measured faster).  Phase 1 makes no vector memory access: its
-        // twiddles come from LDS, because such an access would complete only
-        // after every tile load in flight.
-        if (a + 1 < a0 + na) issue_tile(a + 1, raw[cur ^ 1]);
+        // phase 1 is done with the tile: request the next one.  Phase 1
+        // makes no vector memory access (its twiddles come from LDS), since
+        // such an access would complete only after every tile load in flight.
+        if (a + 1 < a0 + na) issue_tile(a + 1, raw);
         TPRegs<C, N, +1, NLI, NT, true> g;
         g.run(Z, tid);
         __syncthreads();
@@ -833,8 +833,6 @@ __global__ __launch_bounds__(256, 2) void k_xprod(const typename CplxOf<R>::T* _
             Q[4][i] = cmk<C>(Q[4][i].x + sx.x * gz.x, Q[4][i].y + sx.y * gz.y);
             Q[5][i] = cmk<C>(Q[5][i].x + sy.x * gz.x, Q[5][i].y + sy.y * gz.y);
         }
-        // tile a+2 goes into raw[cur] only after phase 1 of term a+1, long
-        // after phase 1 of this term finished reading it
     }
     __syncthreads();
     // forward DFT along x, one component at a time: the P pair lines are

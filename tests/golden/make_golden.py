@@ -52,6 +52,10 @@ FIXTURES = {
     "local256_fp64_oracle": lambda: sampled(
         W.config_local_ng(256, 64), [(0, [20, 33, 44, 60]), (3, [44])], "local256_fp64_oracle",
         "256^3 local NG f_NL=5 (F_NL=3), A=1e-2, sigma=0.5, k*=20, 64 log bins; FP64 oracle"),
+    # 512^3 exponential tail (beta = 3), 96 log bins, seed 0: low tail, peak, high tail
+    "exptail512_fp64_oracle": lambda: sampled(
+        W.config_exptail(512, 96), [(0, [44, 66, 80])], "exptail512_fp64_oracle",
+        "512^3 exp-tail beta=3 clip 1e-6, A=5e-3, sigma=0.3, k*=40, 96 log bins; FP64 oracle"),
 }
 
 if __name__ == "__main__":
