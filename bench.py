@@ -1,14 +1,19 @@
 """Benchmark of the lattice Omega_GW path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--no-cpu]
+                    [--workload local256|exptail512]
 
-One step = the whole hot path for one batch: four realisations (seeds 0..3)
-of a 256^3 local non-Gaussian field (f_NL = 5, i.e. F_NL = 3 with the sample
-<zeta_g^2> subtracted; log-normal A = 1e-2, sigma = 0.5, k* = 20) are
-generated on the device, and Omega_GW is computed in 64 log bins on
-[k_F, k_Nyquist] for each (7 bins hold no lattice mode and cost nothing).
-Fields and FFTs are FP32 (complex64); maps, lookup tables and shell sums are
-FP64.  Inputs (plans, tables) are resident before the timed region.
+Default workload (local256): one step = the whole hot path for one batch:
+four realisations (seeds 0..3) of a 256^3 local non-Gaussian field (f_NL = 5,
+i.e. F_NL = 3 with the sample <zeta_g^2> subtracted; log-normal A = 1e-2,
+sigma = 0.5, k* = 20) are generated on the device, and Omega_GW is computed
+in 64 log bins on [k_F, k_Nyquist] for each (7 bins hold no lattice mode and
+cost nothing).  exptail512: eight realisations (seeds 0..7) of a 512^3
+exponential-tail field (beta = 3, clip 1e-6; A = 5e-3, sigma = 0.3, k* = 40)
+in 96 log bins, averaged over the seeds.  Fields and FFTs are FP32
+(complex64); maps, lookup tables and shell sums are FP64.  Inputs (plans,
+tables) are resident before the timed region.  --fp64 adds the FP64 path on
+seed 0: its speed and the per-bin FP32 error against it.
 
 Prints one JSON line with the throughput in spectra/s (one spectrum = one
 realisation x all its bins), the roofline of the dominant kernel measured
@@ -74,17 +79,37 @@ def algorithmic_bytes(N: int, cb: int, n_alpha: int, n_planes: int):
     }
 
 
+WORKLOADS = {
+    "local256": dict(
+        job=lambda: W.config_local_ng(256, 64),
+        metric="Omega_GW spectra/s (256^3 FP32 fields/FFT, FP64 shell sums)",
+        text="local-NG f_NL=5 log-normal (A=1e-2, sigma=0.5, k*=20), 256^3, L=2pi, "
+             "64 log bins on [k_F, k_Nyq], seeds 0..3"),
+    "exptail512": dict(
+        job=lambda: W.config_exptail(512, 96),
+        metric="Omega_GW spectra/s (512^3 FP32 fields/FFT, FP64 shell sums)",
+        text="exp-tail beta=3 clip 1e-6 log-normal (A=5e-3, sigma=0.3, k*=40), 512^3, L=2pi, "
+             "96 log bins on [k_F, k_Nyq], seeds 0..7 averaged"),
+}
+
+
 def run_gpu(args):
     import torch
     import paper_2605_27231_amd as P
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    job = W.config_local_ng(256, 64)
+    job = WORKLOADS[args.workload]["job"]()
     seeds = list(job.seeds)
     prec = "f32"
-    plan = P.Plan(job.N, L=job.L, prec=prec, n_slots=len(seeds))
+    # the autotuner picks the x-pass schedule at creation (outside the timed region)
+    plan = P.Plan(job.N, L=job.L, prec=prec, n_slots=len(seeds), autotune=1)
+    schedule = plan.schedule()[2]
     cb = 8
+    per_seed = {}
+
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     def step(lat):
         for i, s in enumerate(seeds):
@@ -92,10 +117,10 @@ def run_gpu(args):
             plan.generate_field(i, s, job.spectrum, job.ngmap)
             om, nb = plan.spectrum(i, job.targets, job.k_lo, job.k_hi)
             lat.append(time.perf_counter() - t0)
+            per_seed[s] = om
+            if job.N > 256:
+                say(f"seed {s}: {lat[-1]:.2f} s")
         return om, nb
-
-    def say(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         tw = time.perf_counter()
@@ -142,23 +167,36 @@ def run_gpu(args):
                      "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(ms_d, 4),
                      "launches": n_d},
         "kernels": kernels,
+        "schedule": schedule,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "what": "one spectrum (field generation + 64 bins) end to end"},
+                       "what": f"one spectrum (field generation + {len(job.targets)} bins) end to end"},
+        "omega_seed_mean": np.mean([per_seed[s] for s in seeds], axis=0).tolist(),
+        "targets": job.targets.tolist(),
+        "nmodes": nb.tolist(),
     }
     plan.close()
     if args.fp64:
-        pl64 = P.Plan(job.N, L=job.L, prec="f64", n_slots=1)
-        pl64.generate_field(0, 0, job.spectrum, job.ngmap)
+        pl64 = P.Plan(job.N, L=job.L, prec="f64", n_slots=1, autotune=1)
+        say("FP64 path: warm-up spectrum of seed 0")
+        pl64.generate_field(0, seeds[0], job.spectrum, job.ngmap)
         pl64.spectrum(0, job.targets, job.k_lo, job.k_hi)   # warm
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pl64.generate_field(0, 0, job.spectrum, job.ngmap)
-        om64, _ = pl64.spectrum(0, job.targets, job.k_lo, job.k_hi)
+        pl64.generate_field(0, seeds[0], job.spectrum, job.ngmap)
+        om64, nb64 = pl64.spectrum(0, job.targets, job.k_lo, job.k_hi)
         torch.cuda.synchronize()
         d64 = time.perf_counter() - t1
         pl64.close()
+        say(f"FP64 path: {d64:.2f} s per spectrum")
+        om32 = per_seed[seeds[0]]
+        ok = nb64 > 0
+        rel = np.zeros_like(om64)
+        rel[ok] = np.abs(om32[ok] - om64[ok]) / np.abs(om64[ok])
         res["fp64_path"] = {"spectra_per_s": 1.0 / d64, "speedup_fp32_over_fp64": value * d64,
-                            "what": "seed 0 only, same bins, FP64 fields/FFTs"}
+                            "fp32_rel_err_per_bin": {"max": float(rel.max()), "median": float(np.median(rel[ok])),
+                                                     "bins": [float(x) for x in rel]},
+                            "nmodes_equal": bool(np.array_equal(nb64, nb)),
+                            "what": f"seed {seeds[0]} only, same bins, FP64 fields/FFTs"}
     return res
 
 
@@ -229,6 +267,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true",
                     help="one field + one target + a 1 GiB copy, for hardware-counter passes")
+    ap.add_argument("--workload", default="local256", choices=sorted(WORKLOADS),
+                    help="local256 (the headline line) or exptail512")
     args = ap.parse_args()
     if args.quick:
         quick_profile()
@@ -239,12 +279,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     g = run_gpu(args)
+    wl = WORKLOADS[args.workload]
+    job = wl["job"]()
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "local256":
         print("[bench] oracle CPU baseline sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
     line = {
-        "metric": "Omega_GW spectra/s (256^3 FP32 fields/FFT, FP64 shell sums)",
+        "metric": wl["metric"],
         "value": round(g["value"], 4),
         "unit": "spectra/s",
         "n_gpus": 1,
@@ -256,17 +298,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "local-NG f_NL=5 log-normal (A=1e-2, sigma=0.5, k*=20), 256^3, "
-                               "L=2pi, 64 log bins on [k_F, k_Nyq], seeds 0..3",
-                   "N": 256, "bins": 64, "nonempty_bins": g["n_targets"], "seeds": 4,
+        "config": {"workload": wl["text"], "N": job.N, "bins": len(job.targets),
+                   "nonempty_bins": g["n_targets"], "seeds": len(job.seeds),
                    "n_alpha": 50, "n_modes": 200},
         "roofline": g["roofline"],
         "kernels": g["kernels"],
+        "xprod_schedule": g["schedule"],
         "latency_ms": g["latency_ms"],
         "cpu_baseline": cpu,
     }
     if "fp64_path" in g:
         line["fp64_path"] = g["fp64_path"]
+    if args.workload != "local256":
+        line["omega_seed_mean"] = g["omega_seed_mean"]
+        line["targets"] = g["targets"]
+        line["nmodes"] = g["nmodes"]
     print(json.dumps(line), flush=True)
 
 

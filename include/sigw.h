@@ -76,7 +76,10 @@ typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2 } si
  * staging fits in 16 GiB.  A small count keeps the staging resident in the
  * last-level cache at the price of re-reading Phi_hat per group.  batch is
  * how many realisations one kernel launch processes together (0 = 1); each
- * brings its own workspace, so the footprint grows linearly with it. */
+ * brings its own workspace, so the footprint grows linearly with it.
+ * autotune: 0 = the compiled default x-pass schedule; 1 = at creation, the
+ * schedule the process-wide table holds for this (device, N, precision), or
+ * if there is none, run sigw_autotune (see below). */
 typedef struct {
     int32_t N;
     double  L;
@@ -88,6 +91,7 @@ typedef struct {
     int32_t alpha_chunk;
     int32_t scratch_terms;
     int32_t batch;
+    int32_t autotune;
 } sigw_plan_desc;
 
 /* Log-normal peak, Eq. lognormal: Delta^2(k) = A/sqrt(2 pi sigma^2) exp(-ln^2(k/k_star)/(2 sigma^2)).
@@ -202,6 +206,30 @@ sigw_status sigw_graph_create(sigw_plan_t plan, int32_t n_sel, const int32_t* sl
 sigw_status sigw_graph_launch(sigw_graph_t graph);
 sigw_status sigw_graph_results(sigw_graph_t graph, double* omega_host, int64_t* nmodes_host);
 sigw_status sigw_graph_destroy(sigw_graph_t graph);
+
+/* Project-written autotuner of the x-pass schedule.  The fused kernel that
+ * runs the last inverse pass (x), the products and the first forward pass
+ * reads the most bytes of the path; several schedules of it are compiled
+ * for each N: the z chunk one workgroup transforms (2 to 16 values, which
+ * sets its LDS tile) and the workgroups-per-CU occupancy it is compiled for.
+ * sigw_autotune times each on the plan's own workspace (one launch over
+ * alpha_chunk terms and all kx planes to warm up, then the fastest of three,
+ * HIP events on the plan stream), keeps the fastest, and stores the choice
+ * for this (device, N, precision) in a process-wide table that later plans
+ * created with desc.autotune = 1 reuse.  flags: 0 = reuse the table entry if
+ * there is one, SIGW_TUNE_FORCE = time again.  It overwrites the plan's
+ * workspace and synchronises the plan stream, so it must not run while an
+ * asynchronous spectrum of the plan is in flight (SIGW_E_STATE).  Every
+ * schedule computes the same values in the same order, so results do not
+ * depend on the choice.
+ * sigw_plan_schedule reports the active schedule: its index among the
+ * compiled ones (0 = the default), their count, and a text line
+ * ("tzx=8 occ=3", followed by the measured times after a tuning run; may
+ * be NULL).  sigw_plan_set_schedule selects one by index. */
+#define SIGW_TUNE_FORCE 1
+sigw_status sigw_autotune(sigw_plan_t plan, int32_t flags);
+sigw_status sigw_plan_schedule(sigw_plan_t plan, int32_t* index, int32_t* count, char* text, size_t text_len);
+sigw_status sigw_plan_set_schedule(sigw_plan_t plan, int32_t index);
 
 /* Block until the plan stream is idle. */
 sigw_status sigw_synchronize(sigw_plan_t plan);

@@ -32,7 +32,10 @@ EXPORTS = (
     "sigw_spectrum_batch", "sigw_spectrum_enqueue", "sigw_spectrum_poll", "sigw_synchronize",
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
+    "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule",
 )
+
+SIGW_TUNE_FORCE = 1
 
 
 class PlanDesc(ct.Structure):
@@ -41,7 +44,7 @@ class PlanDesc(ct.Structure):
         ("n_modes", ct.c_int32), ("n_alpha", ct.c_int32),
         ("u_min", ct.c_double), ("u_max", ct.c_double), ("u_p", ct.c_double),
         ("sigma_p", ct.c_double), ("A_p", ct.c_double), ("alpha_chunk", ct.c_int32),
-        ("scratch_terms", ct.c_int32), ("batch", ct.c_int32),
+        ("scratch_terms", ct.c_int32), ("batch", ct.c_int32), ("autotune", ct.c_int32),
     ]
 
 
@@ -100,6 +103,9 @@ def lib() -> ct.CDLL:
         "sigw_graph_launch": [P],
         "sigw_graph_results": [P, D, I64],
         "sigw_graph_destroy": [P],
+        "sigw_autotune": [P, ct.c_int32],
+        "sigw_plan_schedule": [P, I32, I32, ct.c_char_p, ct.c_size_t],
+        "sigw_plan_set_schedule": [P, ct.c_int32],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -32,7 +32,8 @@ def _i64ptr(a: np.ndarray):
 def plan_desc(N: int, L: float = 2 * math.pi, prec: str = "f32", n_slots: int = 1,
               n_modes: int = 200, n_alpha: int = 50, u_min: float = 1e-3, u_max: float = 15.0,
               u_p: float = 1.0, sigma_p: float = 0.5, A_p: float = 10.0,
-              alpha_chunk: int = 0, scratch_terms: int = 0, batch: int = 0) -> _lib.PlanDesc:
+              alpha_chunk: int = 0, scratch_terms: int = 0, batch: int = 0,
+              autotune: int = 0) -> _lib.PlanDesc:
     d = _lib.PlanDesc()
     d.N, d.L, d.prec, d.n_slots = N, L, _prec_code(prec), n_slots
     d.n_modes, d.n_alpha = n_modes, n_alpha
@@ -40,6 +41,7 @@ def plan_desc(N: int, L: float = 2 * math.pi, prec: str = "f32", n_slots: int = 
     d.alpha_chunk = alpha_chunk
     d.scratch_terms = scratch_terms
     d.batch = batch
+    d.autotune = autotune
     return d
 
 
@@ -199,6 +201,22 @@ class Plan:
 
     def graph(self, slots: Sequence[int], targets, k_lo, k_hi) -> "SpectrumGraph":
         return SpectrumGraph(self, slots, targets, k_lo, k_hi)
+
+    # -- x-pass schedule ------------------------------------------------------
+    def autotune(self, force: bool = False) -> str:
+        self._chk(lib().sigw_autotune(self.h, _lib.SIGW_TUNE_FORCE if force else 0), "sigw_autotune")
+        return self.schedule()[2]
+
+    def schedule(self):
+        """(index, count, text) of the active x-pass schedule."""
+        idx, cnt = ct.c_int32(0), ct.c_int32(0)
+        buf = ct.create_string_buffer(512)
+        self._chk(lib().sigw_plan_schedule(self.h, ct.byref(idx), ct.byref(cnt), buf, len(buf)),
+                  "sigw_plan_schedule")
+        return idx.value, cnt.value, buf.value.decode()
+
+    def set_schedule(self, index: int):
+        self._chk(lib().sigw_plan_set_schedule(self.h, int(index)), "sigw_plan_set_schedule")
 
     # -- timing --------------------------------------------------------------
     def set_timing(self, on: bool):

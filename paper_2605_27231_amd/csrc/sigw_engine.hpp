@@ -59,16 +59,24 @@ struct Engine {
                        const void* phi_tab, int n_alpha, int a0, int na, double k_F, double inv_V,
                        void* S, long s_stride, hipStream_t s) = 0;
     // Inverse DFT along y of na terms' (W, Z) pairs into their three gradient
-    // fields T[3a + j]: IDFT_y(W), IDFT_y(i qt_y W), IDFT_y(Z).
+    // fields T[3a + j]: i qt_x IDFT_y(W), IDFT_y(i qt_y W), IDFT_y(Z), stored
+    // in the x-pass tile layout.
     virtual void ypass3(const void* S, int na, int nb, long s_stride, void* T, long t_stride, double k_F,
                         hipStream_t s) = 0;
-    // Fused inverse DFT along x (with i qt_x on the first field of each term)
-    // + products + forward DFT along x:
+    // Fused inverse DFT along x + products + forward DFT along x:
     // Qx_c = DFT_x( sum_a sigma_a dV G_a,i G_a,j ) for the 6 components, on
     // the kx planes [0, n_planes); accumulate adds into Qx instead of storing.
+    // Runs the active x-pass schedule.
     virtual void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na,
                        double dV, double k_F, void* Qx, long q_stride, int n_planes, int accumulate,
                        hipStream_t s) = 0;
+    // x-pass schedules compiled for this size (index 0 is the default): z
+    // chunk width and blocks-per-CU target of schedule i; the active one.
+    // Every schedule computes the same values in the same order.
+    virtual int xprod_schedules() const = 0;
+    virtual void xprod_schedule_info(int i, int* tzx, int* occ) const = 0;
+    virtual void set_xprod_schedule(int i) = 0;
+    virtual int xprod_schedule() const = 0;
     // Fused forward DFT along z of the 12 components (both kernels) + TT
     // projection + shell sums: one (sum, count) partial per block, member b's
     // at [b * zbin_blocks(), (b + 1) * zbin_blocks()).

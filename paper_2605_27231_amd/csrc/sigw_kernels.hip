@@ -30,15 +30,6 @@ template <typename R, int N> struct Shape {
     static constexpr long FS = long(H) * N * N;           // complex elements per half spectrum
     // y-pass / x-pass chunk of contiguous z values (128-byte runs of complex)
     static constexpr int TZ = (sizeof(R) == 4 ? 16 : 8) < N ? (sizeof(R) == 4 ? 16 : 8) : N;
-    // xprod chunk: keeps the LDS tile near 50 KB
-    static constexpr int TZX0 = (N >= 384) ? (sizeof(R) == 4 ? 8 : 4) : (sizeof(R) == 4 ? 8 : 4);
-    static constexpr int TZX = TZX0 < N ? TZX0 : N;
-    static constexpr int PX = TZX / 2;                    // z pairs per xprod tile
-    // threads per xprod block: a divisor of the N * PX point pairs, at most 512
-    static constexpr int NPP = N * PX;
-    static constexpr int NTX = NPP <= 256 ? NPP : (NPP % 256 == 0 ? 256 : (NPP % 192 == 0 ? 192 : 128));
-    static constexpr int PPX = NPP / NTX;                 // point pairs per thread
-    static_assert(NTX * PPX == NPP, "xprod threads must tile the point pairs");
     // z-pass rows per block
     static constexpr int RBZ = (N >= 1024) ? 1 : (N >= 512 ? 4 : (N >= 256 ? 8 : (2048 / N)));
     static constexpr int RBZ_ = (N == 384) ? 4 : RBZ;
@@ -53,6 +44,7 @@ template <typename R, int N> struct Shape {
 
 __device__ __forceinline__ int signed_index(int i, int N) { return i < N / 2 ? i : i - N; }
 
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
 // with its own L2.  xcd_block renumbers the nb blocks of a grid row so that
 // every XCD works through one contiguous range of logical blocks.  The
@@ -63,6 +55,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     const int x = b % 8, s = b / 8;
     const int q = nb / 8, r = nb % 8;
     return x * q + (x < r ? x : r) + s;
+}
+
+// Layout of the gradient fields U (written by ypass3, read by xprod): tiles
+// of TZT z values, 128 bytes.  Element (kx, y, z) of a field sits at
+//   ((y * (N / TZT) + z / TZT) * (N/2 + 1) + kx) * TZT + z % TZT.
+// ypass3 writes whole 128-byte lines per (kx, y); the (N/2+1) x TZT region
+// that the xprod blocks of one (y, z tile) read together is contiguous.  At
+// 512^3 the x pass reads this about twice as fast as the kx-major
+// half-spectrum order, at 256^3 about as fast; 256- and 512-byte tiles and a
+// y-major order measured no better.
+template <typename R, int N> struct TTile {
+    static constexpr int TZT0 = 128 / int(2 * sizeof(R));
+    static constexpr int TZT = TZT0 < N ? TZT0 : N;
+};
+template <int N, int TZT>
+__device__ __forceinline__ long t_offset(int kx, int y, int z) {
+    return ((long(y) * (N / TZT) + z / TZT) * (N / 2 + 1) + kx) * TZT + z % TZT;
 }
 
 // ----------------------------------------------------------------------------
@@ -568,7 +577,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
 // (qt_x is uniform over a block's kx plane, so its factor costs nothing
 // here and leaves the x pass a uniform Hermitian extension).  Tile (term,
 // kx plane, z chunk); the three outputs are transformed one after another
-// through the same LDS tile.
+// through the same LDS tile and stored in the x-pass tile layout (t_offset).
 // ----------------------------------------------------------------------------
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
@@ -580,6 +589,8 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     constexpr int NZC = N / TZ;
     constexpr int H = N / 2 + 1;
     constexpr long FS = Shape<R, N>::FS;
+    constexpr int TZT = TTile<R, N>::TZT;
+    static_assert(TZT % TZ == 0, "a y-pass chunk lies inside one field tile");
     using Lay = TPLayout<N, TZ, true>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = TZ * R2;
@@ -655,8 +666,8 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
             tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, twl, tid);
         }
         __syncthreads();
-        C* dst = T + (3 * al + j) * FS + off;
-        auto st = [&](int zz, int y, C v) { dst[long(y) * N + zz] = v; };
+        C* dst = T + (3 * al + j) * FS;
+        auto st = [&](int zz, int y, C v) { dst[t_offset<N, TZT>(kx, y, zc * TZ + zz)] = v; };
         tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tid);
         __syncthreads();
     }
@@ -677,18 +688,44 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
 // is applied when phase 1 reads the tile back (the gradient factors were
 // applied by the earlier passes).
 // ----------------------------------------------------------------------------
-template <typename R, int N>
-__global__ __launch_bounds__(256, 3) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
+// x-pass schedule: TZX z values (TZX/2 pairs) per block, a part of one
+// gradient-field tile; threads: a divisor of the N TZX/2 point pairs, at
+// most 256.  LDS: raw tile, phase-1 transpose / G lines, twiddle copy.
+template <typename R, int N, int TZX_> struct XShape {
+    static constexpr int TZX = TZX_ < N ? TZX_ : N;
+    static constexpr int PX = TZX / 2;
+    static constexpr int NPP = N * PX;
+    static constexpr int NTX = NPP <= 256 ? NPP : (NPP % 256 == 0 ? 256 : (NPP % 192 == 0 ? 192 : 128));
+    static constexpr int PPX = NPP / NTX;                 // point pairs per thread
+    static_assert(NTX * PPX == NPP, "xprod threads must tile the point pairs");
+    static constexpr int LS = N + 2;
+    static constexpr int NLI = 3 * PX;
+    static constexpr long LDS = (2L * 3 * (N / 2 + 1) * PX + CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v + N) *
+                                long(2 * sizeof(R));
+};
+
+// The schedule compiled as the default for each size: an 8-wide chunk in
+// FP32 (a 4-wide one in FP64) keeps the LDS near 52 KB at 256^3 and lets
+// three blocks share a CU; from 384^3 on, 4-wide chunks keep two.
+template <typename R, int N> struct XDefault {
+    static constexpr int TZX0 = (N >= 384) ? 4 : (sizeof(R) == 4 ? 8 : 4);
+    static constexpr int TZX = TZX0 < N ? TZX0 : N;
+    static constexpr int OCC = N >= 384 ? 2 : 3;
+};
+
+template <typename R, int N, int TZX_, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
                                                   const R* __restrict__ sigma, int a0, int na, R dV, R k_F,
                                                   typename CplxOf<R>::T* __restrict__ Q_all, long q_stride,
                                                   int n_planes, int accumulate,
                                                   const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using S = Shape<R, N>;
-    constexpr int TZ = S::TZX;
-    constexpr int P = S::PX;
-    constexpr int NT = S::NTX;
-    constexpr int PP = S::PPX;
+    using X = XShape<R, N, TZX_>;
+    constexpr int TZ = X::TZX;
+    constexpr int P = X::PX;
+    constexpr int NT = X::NTX;
+    constexpr int PP = X::PPX;
     constexpr int NZC = N / TZ;
     constexpr int H = N / 2 + 1;
     constexpr long FS = S::FS;
@@ -715,7 +752,11 @@ __global__ __launch_bounds__(256, 3) void k_xprod(const typename CplxOf<R>::T* _
 #pragma unroll
         for (int i = 0; i < PP; ++i) Q[c][i] = cmk<C>(R(0), R(0));
 
-    const C* col0 = T + long(y) * N + z0;
+    // this block's part of a gradient-field tile (t_offset): one run of TZ
+    // z values per kx, TZT apart
+    constexpr int TZT = TTile<R, N>::TZT;
+    static_assert(TZT % TZ == 0, "an x-pass chunk lies inside one field tile");
+    const C* col0 = T + t_offset<N, TZT>(0, y, z0);
     // 16-byte units: a raw element (two complex) is 1 unit in FP32, 2 in FP64
     constexpr int UPE = int(2 * sizeof(C) / 16);
     constexpr int NU = NRAW * UPE;
@@ -733,7 +774,7 @@ __global__ __launch_bounds__(256, 3) void k_xprod(const typename CplxOf<R>::T* _
         const int j = e / (H * P);
         const int rem = e - j * (H * P);
         const int k = rem / P, p = rem - k * P;
-        uoff[i] = unsigned((long(j) * FS + long(k) * N * N + 2 * p) * long(sizeof(C)) + 16 * h);
+        uoff[i] = unsigned((long(j) * FS + long(k) * TZT + 2 * p) * long(sizeof(C)) + 16 * h);
     }
     auto issue_tile = [&](int a, C* dst) {
         const char* colf = reinterpret_cast<const char*>(col0 + long(3 * (a - a0)) * FS);
@@ -1049,7 +1090,7 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     using C = typename CplxOf<R>::T;
     using S = Shape<R, NN>;
     const C* tw;
-    explicit EngineImpl(const void* twd) : tw(static_cast<const C*>(twd)) {}
+    explicit EngineImpl(const void* twd) : tw(static_cast<const C*>(twd)) { add_schedules(); }
 
     int N() const override { return NN; }
     size_t real_bytes() const override { return sizeof(R); }
@@ -1125,10 +1166,46 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     }
     void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na, double dV, double k_F,
                void* Qx, long q_stride, int n_planes, int accumulate, hipStream_t s) override {
-        const unsigned blocks = unsigned(NN * (NN / S::TZX));
-        k_xprod<R, NN><<<dim3(blocks, unsigned(nb)), dim3(S::NTX), 0, s>>>(
-            static_cast<const C*>(T), t_stride, static_cast<const R*>(sigma_tab), a0, na, R(dV), R(k_F),
-            static_cast<C*>(Qx), q_stride, n_planes, accumulate, tw);
+        xs_[xsel_].fn(static_cast<const C*>(T), t_stride, nb, static_cast<const R*>(sigma_tab), a0, na, R(dV),
+                      R(k_F), static_cast<C*>(Qx), q_stride, n_planes, accumulate, tw, s);
+    }
+    int xprod_schedules() const override { return nxs_; }
+    void xprod_schedule_info(int i, int* tzx, int* occ) const override {
+        *tzx = xs_[i].tzx;
+        *occ = xs_[i].occ;
+    }
+    void set_xprod_schedule(int i) override { xsel_ = i; }
+    int xprod_schedule() const override { return xsel_; }
+
+    // x-pass schedules compiled for this size: entry 0 is the default, the
+    // others differ in chunk width (half, double) and blocks-per-CU target.
+    using XFn = void (*)(const C*, long, int, const R*, int, int, R, R, C*, long, int, int, const C*, hipStream_t);
+    struct XSched {
+        int tzx, occ;
+        XFn fn;
+    };
+    XSched xs_[3];
+    int nxs_ = 0, xsel_ = 0;
+    template <int TZX, int OCC>
+    static void xlaunch(const C* T, long t_stride, int nb, const R* sigma, int a0, int na, R dV, R kF, C* Qx,
+                        long q_stride, int n_planes, int acc, const C* twd, hipStream_t s) {
+        using X = XShape<R, NN, TZX>;
+        const unsigned blocks = unsigned(NN * (NN / X::TZX));
+        k_xprod<R, NN, TZX, OCC><<<dim3(blocks, unsigned(nb)), dim3(X::NTX), 0, s>>>(
+            T, t_stride, sigma, a0, na, dV, kF, Qx, q_stride, n_planes, acc, twd);
+    }
+    template <int TZX, int OCC> void add_schedule() {
+        using X = XShape<R, NN, TZX>;
+        if constexpr (TZX >= 2 && TZX <= NN && TTile<R, NN>::TZT % TZX == 0 && X::LDS <= 160 * 1024)
+            xs_[nxs_++] = {X::TZX, OCC, &xlaunch<TZX, OCC>};
+    }
+    void add_schedules() {
+        using D = XDefault<R, NN>;
+        add_schedule<D::TZX, D::OCC>();
+        if constexpr (NN >= 64) {
+            add_schedule<D::TZX / 2, D::OCC>();
+            add_schedule<D::TZX * 2, (D::OCC > 1 ? D::OCC - 1 : 1)>();
+        }
     }
     void zbin(const void* Qxy, int nb, long q_stride, const uint8_t* lut_shell, int n2_lo, int n2_hi, double* ps,
               unsigned long long* pc, hipStream_t s) override {

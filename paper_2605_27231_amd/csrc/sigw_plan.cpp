@@ -7,10 +7,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sigw.h"
@@ -173,6 +176,7 @@ const char* validate(const sigw_plan_desc* d) {
     if (d->alpha_chunk < 0 || d->alpha_chunk > d->n_alpha) return "alpha_chunk must be in [0, n_alpha]";
     if (d->scratch_terms < 0 || d->scratch_terms > d->n_alpha) return "scratch_terms must be in [0, n_alpha]";
     if (d->batch < 0 || d->batch > 4096) return "batch must be in [0, 4096]";
+    if (d->autotune != 0 && d->autotune != 1) return "autotune must be 0 or 1";
     return nullptr;
 }
 
@@ -241,6 +245,7 @@ struct sigw_plan {
     int device = 0;
     std::unique_ptr<sigw::Engine> eng;
     std::string err;
+    std::string schedule;       // report of the active x-pass schedule
     std::vector<double> edges_h;
     Table tab_h[2];
     // device buffers
@@ -493,6 +498,93 @@ sigw_status check_slot(sigw_plan* p, int slot, bool need_field) {
 
 }  // namespace
 
+namespace {
+
+// Process-wide choices of the x-pass schedule per (device, N, precision):
+// index and report line.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, std::string>> g_tune;
+
+std::string schedule_name(sigw::Engine* e, int i) {
+    int tzx = 0, occ = 0;
+    e->xprod_schedule_info(i, &tzx, &occ);
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "tzx=%d occ=%d", tzx, occ);
+    return buf;
+}
+
+// Time every compiled x-pass schedule on the plan's workspace and keep the
+// fastest (see sigw_autotune in the header).
+sigw_status tune_xprod(sigw_plan* p, int flags) {
+    const auto key = std::make_tuple(p->device, p->d.N, p->d.prec);
+    sigw::Engine* e = p->eng.get();
+    const int n = e->xprod_schedules();
+    if (!(flags & SIGW_TUNE_FORCE)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && it->second.first < n) {
+            e->set_xprod_schedule(it->second.first);
+            p->schedule = it->second.second;
+            return SIGW_OK;
+        }
+    }
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    const double kF = 2.0 * kPi / d.L;
+    const double V = d.L * d.L * d.L;
+    const double dV = V / double(z.R3);
+    const long t_stride = long(3) * z.chunk * z.FS;
+    const long q_stride = long(12) * z.FS;
+    const int na = std::min(z.chunk, d.n_alpha);
+    // defined contents for the timing launches (the values do not matter)
+    HIP_TRY(p, hipMemsetAsync(p->T, 0, size_t(t_stride) * z.cb, p->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(p, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(p, SIGW_E_DEVICE, "hipEventCreate failed");
+    }
+    std::vector<float> best(n, 0.0f);
+    sigw_status st = SIGW_OK;
+    for (int i = 0; i < n && st == SIGW_OK; ++i) {
+        e->set_xprod_schedule(i);
+        e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, p->stream);
+        for (int r = 0; r < 3 && st == SIGW_OK; ++r) {
+            float ms = 0.0f;
+            if (hipEventRecord(e0, p->stream) != hipSuccess) st = SIGW_E_DEVICE;
+            e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, p->stream);
+            if (st == SIGW_OK && (hipEventRecord(e1, p->stream) != hipSuccess ||
+                                  hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = SIGW_E_DEVICE;
+            if (st == SIGW_OK && (r == 0 || ms < best[i])) best[i] = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SIGW_OK) {
+        e->set_xprod_schedule(0);
+        return fail(p, st, "x-pass schedule timing failed");
+    }
+    int pick = 0;
+    for (int i = 1; i < n; ++i)
+        if (best[i] < best[pick]) pick = i;
+    e->set_xprod_schedule(pick);
+    std::string rep = schedule_name(e, pick) + " (timed over " + std::to_string(na) + " terms:";
+    for (int i = 0; i < n; ++i) {
+        char buf[96];
+        std::snprintf(buf, sizeof buf, " %s %.3f ms%s", schedule_name(e, i).c_str(), double(best[i]),
+                      i + 1 < n ? "," : ")");
+        rep += buf;
+    }
+    p->schedule = rep;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {pick, rep};
+    return SIGW_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sigw_status_string(sigw_status s) {
@@ -527,6 +619,7 @@ sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32
     d->alpha_chunk = 0;
     d->scratch_terms = 0;
     d->batch = 0;
+    d->autotune = 0;
     return SIGW_OK;
 }
 
@@ -666,6 +759,14 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
     if (!P->eng) {
         sigw_plan_destroy(p.release());
         return SIGW_E_UNSUPPORTED;
+    }
+    P->schedule = schedule_name(P->eng.get(), 0);
+    if (d->autotune) {
+        const sigw_status st = tune_xprod(P, 0);
+        if (st != SIGW_OK) {
+            sigw_plan_destroy(p.release());
+            return st;
+        }
     }
     *out = p.release();
     return SIGW_OK;
@@ -970,6 +1071,37 @@ sigw_status sigw_graph_results(sigw_graph_t gr, double* omega, int64_t* nmodes) 
         to_omega(p, gr->n_k, gr->kt.data(), gr->h_sums + size_t(i) * gr->n_k, gr->h_cnts + size_t(i) * gr->n_k,
                  gr->valid.data(), omega ? omega + size_t(i) * gr->n_k : nullptr,
                  nmodes ? nmodes + size_t(i) * gr->n_k : nullptr);
+    return SIGW_OK;
+}
+
+sigw_status sigw_autotune(sigw_plan_t p, int32_t flags) {
+    if (!p) return SIGW_E_INVALID;
+    if (flags & ~int32_t(SIGW_TUNE_FORCE)) return fail(p, SIGW_E_INVALID, "unknown autotune flags");
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return tune_xprod(p, flags);
+}
+
+sigw_status sigw_plan_schedule(sigw_plan_t p, int32_t* index, int32_t* count, char* text, size_t text_len) {
+    if (!p) return SIGW_E_INVALID;
+    if (index) *index = p->eng->xprod_schedule();
+    if (count) *count = p->eng->xprod_schedules();
+    if (text && text_len > 0) {
+        const size_t n = std::min(text_len - 1, p->schedule.size());
+        std::memcpy(text, p->schedule.data(), n);
+        text[n] = '\0';
+    }
+    return SIGW_OK;
+}
+
+sigw_status sigw_plan_set_schedule(sigw_plan_t p, int32_t index) {
+    if (!p) return SIGW_E_INVALID;
+    if (index < 0 || index >= p->eng->xprod_schedules())
+        return fail(p, SIGW_E_INVALID, "schedule index out of range");
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->eng->set_xprod_schedule(index);
+    p->schedule = schedule_name(p->eng.get(), index);
     return SIGW_OK;
 }
 

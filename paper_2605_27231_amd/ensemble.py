@@ -53,6 +53,7 @@ class Ensemble:
         # a graph needs a real (non-null) stream
         self.stream = stream if stream is not None else (torch.cuda.Stream() if graph else None)
         j0 = self.jobs[0]
+        decomp.setdefault("autotune", 1)
         self.plan = Plan(j0.N, L=j0.L, prec=prec, n_slots=self.group, batch=self.batch,
                          stream=self.stream, **decomp)
         self.slots = list(range(self.group))
@@ -116,12 +117,14 @@ def main():
     args = ap.parse_args()
     jobs = W.config_ensemble(args.N, args.n, args.bins)
     with Ensemble(jobs, prec=args.prec, batch=args.batch, graph=not args.no_graph) as ens:
+        sched = ens.plan.schedule()[2]
         ens.run()
         res = ens.run()
     nonempty = int((res.nmodes[0] > 0).sum())
     print(json.dumps({"workload": f"{args.n} realisations at {args.N}^3, {args.bins} log bins "
                                   f"({nonempty} non-empty), {args.prec}",
-                      "batch": args.batch, "graph": not args.no_graph, "seconds": res.seconds,
+                      "batch": args.batch, "graph": not args.no_graph, "xprod_schedule": sched,
+                      "seconds": res.seconds,
                       "spectra_per_s": res.spectra_per_s,
                       "target_evaluations_per_s": res.spectra_per_s * nonempty}), flush=True)
 

@@ -53,7 +53,7 @@ class GpuBackend:
 
     def _desc(self, N):
         from .api import plan_desc
-        return plan_desc(N, prec=self.prec, alpha_chunk=self.chunk_for(N))
+        return plan_desc(N, prec=self.prec, alpha_chunk=self.chunk_for(N), autotune=1)
 
     def footprint(self, N: int) -> int:
         from .api import sigw_plan_footprint
@@ -68,7 +68,7 @@ class _GpuPlan:
         import torch
         from .api import Plan
         self.stream = torch.cuda.Stream()
-        self.plan = Plan(N, prec=prec, n_slots=1, alpha_chunk=chunk, stream=self.stream)
+        self.plan = Plan(N, prec=prec, n_slots=1, alpha_chunk=chunk, stream=self.stream, autotune=1)
 
     def submit(self, job):
         self.plan.generate_field(0, int(job.seeds[0]), job.spectrum, job.ngmap)

@@ -52,7 +52,7 @@ def test_desc_default_and_validation():
     for field, val in (("N", 100), ("N", 0), ("L", -1.0), ("prec", 3), ("n_slots", 0),
                        ("n_alpha", 201), ("n_alpha", 0), ("u_min", 0.0), ("u_max", 1e-4),
                        ("sigma_p", 0.0), ("alpha_chunk", 51), ("scratch_terms", -1),
-                       ("scratch_terms", 51)):
+                       ("scratch_terms", 51), ("autotune", 2), ("autotune", -1)):
         dd = P.plan_desc(64)
         setattr(dd, field, val)
         bad.append(L.sigw_plan_create(ct.byref(dd), None, ct.byref(out)))
@@ -65,6 +65,9 @@ def test_desc_default_and_validation():
     assert L.sigw_spectrum(None, 0, 0, None, None, None, None, None) == _lib.SIGW_E_INVALID
     assert L.sigw_synchronize(None) == _lib.SIGW_E_INVALID
     assert L.sigw_plan_destroy(None) == _lib.SIGW_E_INVALID
+    assert L.sigw_autotune(None, 0) == _lib.SIGW_E_INVALID
+    assert L.sigw_plan_set_schedule(None, 0) == _lib.SIGW_E_INVALID
+    assert L.sigw_plan_schedule(None, None, None, None, 0) == _lib.SIGW_E_INVALID
 
 
 def test_footprint_formula():
