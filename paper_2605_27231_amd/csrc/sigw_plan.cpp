@@ -162,6 +162,31 @@ Table build_table(const sigw_plan_desc& d, const std::vector<double>& e, int m) 
     return t;
 }
 
+// The tables depend only on the decomposition meta-parameters, and building
+// them (two 200 x 200 eigen-decompositions) costs about half a second: plans
+// created later in the process with the same parameters reuse them.
+struct Decomposition {
+    std::vector<double> edges;
+    Table tab[2];
+};
+using DecompKey = std::tuple<int, int, double, double, double, double, double>;
+std::mutex g_decomp_mu;
+std::map<DecompKey, std::shared_ptr<const Decomposition>> g_decomp;
+
+std::shared_ptr<const Decomposition> decomposition_of(const sigw_plan_desc& d) {
+    const DecompKey key{d.n_modes, d.n_alpha, d.u_min, d.u_max, d.u_p, d.sigma_p, d.A_p};
+    {
+        std::lock_guard<std::mutex> lk(g_decomp_mu);
+        auto it = g_decomp.find(key);
+        if (it != g_decomp.end()) return it->second;
+    }
+    auto dec = std::make_shared<Decomposition>();
+    dec->edges = grid_edges(d);
+    for (int m = 0; m < 2; ++m) dec->tab[m] = build_table(d, dec->edges, m);
+    std::lock_guard<std::mutex> lk(g_decomp_mu);
+    return g_decomp.emplace(key, std::move(dec)).first->second;
+}
+
 const char* validate(const sigw_plan_desc* d) {
     if (!d) return "NULL plan description";
     if (!supported_N(d->N)) return "N must be one of 8, 16, 32, 64, 128, 256, 384, 512";
@@ -632,13 +657,11 @@ sigw_status sigw_plan_footprint(const sigw_plan_desc* d, size_t* bytes) {
 sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma, double* phi, double* edges) {
     if (validate(d) || (m != 0 && m != 1)) return SIGW_E_INVALID;
     try {
-        std::vector<double> e = grid_edges(*d);
-        if (edges) std::copy(e.begin(), e.end(), edges);
-        if (sigma || phi) {
-            Table t = build_table(*d, e, m);
-            if (sigma) std::copy(t.sigma.begin(), t.sigma.end(), sigma);
-            if (phi) std::copy(t.phi.begin(), t.phi.end(), phi);
-        }
+        const std::shared_ptr<const Decomposition> dec = decomposition_of(*d);
+        if (edges) std::copy(dec->edges.begin(), dec->edges.end(), edges);
+        const Table& t = dec->tab[m];
+        if (sigma) std::copy(t.sigma.begin(), t.sigma.end(), sigma);
+        if (phi) std::copy(t.phi.begin(), t.phi.end(), phi);
     } catch (const std::bad_alloc&) {
         return SIGW_E_NOMEM;
     }
@@ -678,10 +701,11 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
     p->z = sizes_of(*d);
     p->stream = static_cast<hipStream_t>(hip_stream);
     p->has_field.assign(d->n_slots, 0);
-    // Sec. V tables on the host
+    // Sec. V tables on the host (built once per parameter set in the process)
     try {
-        p->edges_h = grid_edges(*d);
-        for (int m = 0; m < 2; ++m) p->tab_h[m] = build_table(*d, p->edges_h, m);
+        const std::shared_ptr<const Decomposition> dec = decomposition_of(*d);
+        p->edges_h = dec->edges;
+        for (int m = 0; m < 2; ++m) p->tab_h[m] = dec->tab[m];
     } catch (const std::bad_alloc&) {
         return SIGW_E_NOMEM;
     }

@@ -82,10 +82,18 @@ class _GpuPlan:
 
 
 class SpectrumServer:
+    """max_inflight bounds the requests on the device at once and
+    max_plans_per_size the plans kept per lattice size: the device has a few
+    hardware queues, so more concurrent streams add memory and host work
+    (plan creation) without adding throughput."""
+
     def __init__(self, backend, budget_bytes: int, clock: Callable[[], float] = time.perf_counter,
-                 idle_wait: Callable[[float], None] = time.sleep, prewarm: Optional[Dict[int, int]] = None):
+                 idle_wait: Callable[[float], None] = time.sleep, prewarm: Optional[Dict[int, int]] = None,
+                 max_inflight: int = 8, max_plans_per_size: int = 4):
         self.backend = backend
         self.budget = int(budget_bytes)
+        self.max_inflight = int(max_inflight)
+        self.max_plans_per_size = int(max_plans_per_size)
         self.clock = clock
         self.idle_wait = idle_wait
         self.used = 0
@@ -95,7 +103,7 @@ class SpectrumServer:
         self.peak_used = 0
         self.peak_inflight = 0
         for N, n in (prewarm or {}).items():
-            for _ in range(n):
+            for _ in range(min(n, self.max_plans_per_size)):
                 if not self._create(N):
                     break
 
@@ -132,6 +140,8 @@ class SpectrumServer:
         ps = self.free.get(N)
         if ps:
             return ps.pop()
+        if self.n_plans.get(N, 0) >= self.max_plans_per_size:
+            return None
         fp = self.backend.footprint(N)
         if fp > self.budget:
             raise ValueError(f"a plan for N={N} needs {fp} bytes, more than the whole budget")
@@ -149,9 +159,10 @@ class SpectrumServer:
         self.used = 0
 
     # -- the loop ----------------------------------------------------------------
-    def serve(self, requests) -> List[Served]:
+    def serve(self, requests, progress: Optional[Callable[[int, int], None]] = None) -> List[Served]:
         """requests: objects with rid, arrival (seconds after start) and job,
-        in arrival order.  Returns one Served per request, in finish order."""
+        in arrival order.  Returns one Served per request, in finish order.
+        progress(done, total) is called after every 250th completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             if self.backend.footprint(r.job.N) > self.budget:
@@ -169,6 +180,8 @@ class SpectrumServer:
             admitted = False
             # first fit over the waiting requests, oldest first
             for req in list(waiting):
+                if len(busy) >= self.max_inflight:
+                    break
                 plan = self._acquire(req.job.N)
                 if plan is None:
                     continue
@@ -190,6 +203,8 @@ class SpectrumServer:
                 self.free.setdefault(plan._N, []).append(plan)
                 self.idle_since[id(plan)] = self.clock()
                 finished = True
+                if progress is not None and len(done) % 250 == 0:
+                    progress(len(done), len(reqs))
             if not admitted and not finished:
                 # nothing moved: wait a little, never past the next arrival
                 nxt = reqs[i].arrival - (self.clock() - t0) if i < len(reqs) else math.inf
@@ -226,6 +241,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--prec", default="f32")
     ap.add_argument("--sizes", default="64,128,256,384")
+    ap.add_argument("--max-inflight", type=int, default=8)
+    ap.add_argument("--plans-per-size", type=int, default=4)
     args = ap.parse_args()
     sizes = tuple(int(s) for s in args.sizes.split(","))
     weights = {64: 0.4, 128: 0.3, 256: 0.2, 384: 0.1}
@@ -234,16 +251,20 @@ def main():
     backend = GpuBackend(args.prec)
     prewarm = {64: 4, 128: 4, 256: 3, 384: 2}
     server = SpectrumServer(backend, int(args.budget_gb * 1e9),
-                            prewarm={n: prewarm.get(n, 1) for n in sizes})
+                            prewarm={n: min(prewarm.get(n, 1), args.plans_per_size) for n in sizes},
+                            max_inflight=args.max_inflight, max_plans_per_size=args.plans_per_size)
     # warm every pooled plan once so that first-use costs stay out of the timing
     warm = [W.Request(rid=-1 - k, arrival=0.0, job=r.job) for k, r in enumerate(reqs[:8])]
     server.serve(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = server.serve(reqs)
+    done = server.serve(reqs, progress=lambda d, n: print(f"[serve] {d}/{n} done at "
+                                                        f"{time.perf_counter() - t0:.1f} s",
+                                                        file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     out = summarize(done, wall)
     out.update({"rate": args.rate, "sizes": sizes, "prec": args.prec, "budget_gb": args.budget_gb,
+                "max_inflight": args.max_inflight, "plans_per_size": args.plans_per_size,
                 "peak_inflight": server.peak_inflight, "plans": server.n_plans,
                 "targets_per_request": int(len(reqs[0].job.targets))})
     print(json.dumps(out), flush=True)

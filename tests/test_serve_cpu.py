@@ -2,7 +2,8 @@
 clock: every request completes, admission respects the HBM budget, idle
 plans of other sizes are released for a larger request, requests of one
 size overlap on several plans, latencies are accounted from arrival, and a
-request that can never fit is refused up front."""
+request that can never fit is refused up front; the caps on requests in
+flight and plans per size hold."""
 from dataclasses import dataclass
 
 import numpy as np
@@ -76,10 +77,12 @@ class FakeBackend:
         return Plan()
 
 
-def _run(reqs, budget, prewarm=None):
+def _run(reqs, budget, prewarm=None, **caps):
     clk = SimClock()
     be = FakeBackend(clk)
-    srv = SpectrumServer(be, budget, clock=clk, idle_wait=clk.wait, prewarm=prewarm)
+    caps.setdefault("max_inflight", 100)
+    caps.setdefault("max_plans_per_size", 100)
+    srv = SpectrumServer(be, budget, clock=clk, idle_wait=clk.wait, prewarm=prewarm, **caps)
     done = srv.serve(reqs)
     return srv, be, done
 
@@ -130,3 +133,17 @@ def test_prewarm_and_oversized_request():
     assert be.created == [64, 64, 128]          # the rest of the pool would exceed the budget
     with pytest.raises(ValueError):
         srv.serve([Req(0, 0.0, FakeJob(384, 0))])
+
+
+def test_inflight_and_per_size_caps():
+    reqs = [Req(i, 0.0, FakeJob(64, i)) for i in range(10)]
+    srv, be, done = _run(reqs, budget=100, max_inflight=8, max_plans_per_size=2)
+    assert len(done) == 10 and be.created == [64, 64] and srv.peak_inflight == 2
+    mixed = [Req(i, 0.0, FakeJob([32, 64, 128][i % 3], i)) for i in range(9)]
+    srv, be, done = _run(mixed, budget=100, max_inflight=3, max_plans_per_size=4)
+    assert len(done) == 9 and srv.peak_inflight == 3
+    progress = []
+    clk = SimClock()
+    srv = SpectrumServer(FakeBackend(clk), 100, clock=clk, idle_wait=clk.wait)
+    srv.serve([Req(i, 0.0, FakeJob(32, i)) for i in range(500)], progress=lambda d, n: progress.append((d, n)))
+    assert progress == [(250, 500), (500, 500)]
