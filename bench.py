@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (scaled by a 1 GiB copy: reads x2.0, writes x1.0), valid only for the
 # kernel source they were taken on; see profiles/hbm_counters_localNG256_fp32.md.
-COUNTER_SOURCE_SHA = "151d0df02fed5aef"
-COUNTER_TRAFFIC = {"xprod": 20367920171.5, "ypass": 19300594466.5, "gen_z": 6840692284.5}
+COUNTER_SOURCE_SHA = "462ff91324736580"
+COUNTER_TRAFFIC = {"xprod": 10274046397.5, "ypass": 16908177587.9, "gen_z": 6841149522.0}
 
 
 def kernel_source_sha() -> str:
@@ -274,9 +274,10 @@ def main():
         quick_profile()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU mode "
-              "(targets, seeds and realisations shard trivially across GPUs, see the design notes)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the path has no multi-GPU mode.  Realisations and "
+              "target bins are independent units whose only output is a few KB of shell sums, so "
+              "several GPUs would each take a share of them (one process per GPU) and the host "
+              "would gather the sums.", file=sys.stderr)
         sys.exit(2)
     g = run_gpu(args)
     wl = WORKLOADS[args.workload]
