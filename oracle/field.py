@@ -10,6 +10,11 @@
 * Maps (Sec. VI B and the exponential-tail workload):
   local    zeta = zeta_g + F_NL (zeta_g^2 - m2) + G_NL zeta_g^3, m2 = sample mean of zeta_g^2
   exptail  zeta = -ln(max(1 - beta zeta_g, clip)) / beta
+* Non-local map, Eq. (nonlocal) (Sec. VI C):
+  zeta = zeta_g + (alpha_NL / k_NL^2) lap(zeta_g^2) + (beta_NL / k_NL^2) zeta_g lap(zeta_g),
+  with the spectral Laplacian lap X = IDFT(-|q|^2 DFT X), q = k_F n for the
+  signed index n; |q|^2 is even in every component, so the Nyquist index
+  keeps its own value (reading R23).
 * Potential at w = 1/3: Phi = 3(1+w)/(5+3w) zeta = 2 zeta / 3 (Sec. II), and
   Phi_hat = dV DFT(Phi).
 """
@@ -47,8 +52,21 @@ def gaussian_zeta(N: int, L: float, seed: int, spectrum, noise: np.ndarray = Non
     return lattice.inverse(amp * what, L)
 
 
-def apply_map(zeta_g: np.ndarray, ngmap) -> np.ndarray:
+def laplacian(X: np.ndarray, L: float) -> np.ndarray:
+    """Spectral Laplacian of a real periodic field: IDFT(-k_F^2 |n|^2 DFT(X))."""
+    N = X.shape[0]
+    n2 = lattice.n2_half(N).astype(np.float64)
+    return lattice.inverse(-(lattice.kf(L) ** 2) * n2 * lattice.forward(X, L), L)
+
+
+def apply_map(zeta_g: np.ndarray, ngmap, L: float = None) -> np.ndarray:
     kind = ngmap.kind
+    if kind == "nonlocal":
+        if L is None:
+            raise ValueError("the non-local map needs the box size L")
+        c = 1.0 / (ngmap.k_NL * ngmap.k_NL)
+        return (zeta_g + ngmap.alpha_NL * c * laplacian(zeta_g * zeta_g, L)
+                + ngmap.beta_NL * c * zeta_g * laplacian(zeta_g, L))
     if kind == "gauss":
         return zeta_g.copy()
     if kind == "local":
@@ -67,4 +85,4 @@ def phi_hat_from_zeta(zeta: np.ndarray, L: float) -> np.ndarray:
 
 def phi_hat(N: int, L: float, seed: int, spectrum, ngmap) -> np.ndarray:
     zg = gaussian_zeta(N, L, seed, spectrum)
-    return phi_hat_from_zeta(apply_map(zg, ngmap), L)
+    return phi_hat_from_zeta(apply_map(zg, ngmap, L), L)

@@ -87,3 +87,75 @@ def test_maps():
     out = field.apply_map(big, W.NGMap("exptail", beta=3.0, clip=1e-6))
     assert out[0, 0, 0] == pytest.approx(-math.log(1e-6) / 3.0)
     assert out[0, 0, 1] == pytest.approx(-math.log(0.7) / 3.0)
+
+
+# ------------------------------------------------------------- non-local map
+def _grid(N, L):
+    x = np.arange(N) * (L / N)
+    return np.meshgrid(x, x, x, indexing="ij")
+
+
+def test_nonlocal_map_reduces_to_gaussian():
+    zg = field.gaussian_zeta(16, 2 * math.pi, 3, W.Lognormal(1e-2, 0.5, 3.0))
+    m = W.NGMap("nonlocal", alpha_NL=0.0, beta_NL=0.0, k_NL=3.0)
+    np.testing.assert_array_equal(field.apply_map(zg, m, 2 * math.pi), zg)
+
+
+def test_nonlocal_map_plane_wave_closed_form():
+    """Eq. nonlocal for zeta_g = A cos(q.x): lap(zeta_g^2) = -2|q|^2 A^2 cos(2 q.x)
+    and zeta_g lap(zeta_g) = -|q|^2 A^2 cos^2(q.x), in a box with k_F = 0.5."""
+    N, L, A = 16, 4 * math.pi, 0.3
+    n = np.array([2, -1, 3])                       # 2n stays inside [-N/2, N/2)
+    q = n * (2 * math.pi / L)
+    X, Y, Z = _grid(N, L)
+    ph = q[0] * X + q[1] * Y + q[2] * Z
+    zg = A * np.cos(ph)
+    a, b, kn = 0.7, -1.3, 3.0
+    got = field.apply_map(zg, W.NGMap("nonlocal", alpha_NL=a, beta_NL=b, k_NL=kn), L)
+    qq = float(q @ q)
+    ref = zg + a / kn ** 2 * (-2 * qq * A * A * np.cos(2 * ph)) + b / kn ** 2 * (-qq * A * A * np.cos(ph) ** 2)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _fd4_laplacian(F, h):
+    """Fourth-order central differences, periodic."""
+    out = np.zeros_like(F)
+    for ax in range(3):
+        out += (-np.roll(F, 2, ax) + 16 * np.roll(F, 1, ax) - 30 * F + 16 * np.roll(F, -1, ax)
+                - np.roll(F, -2, ax)) / (12 * h * h)
+    return out
+
+
+def _fd4_grad2(F, h):
+    g2 = np.zeros_like(F)
+    for ax in range(3):
+        d = (-np.roll(F, -2, ax) + 8 * np.roll(F, -1, ax) - 8 * np.roll(F, 1, ax) + np.roll(F, 2, ax)) / (12 * h)
+        g2 += d * d
+    return g2
+
+
+def test_nonlocal_laplacian_against_finite_differences():
+    """A smooth field (modes |n_i| <= 2 only) on 48^3: the spectral Laplacian
+    of zeta_g^2 and of zeta_g agrees with fourth-order finite differences, and
+    the mean of zeta_g lap(zeta_g) equals -mean |grad zeta_g|^2 (integration
+    by parts, gradient by finite differences)."""
+    N, L = 48, 2 * math.pi
+    h = L / N
+    rs = np.random.Generator(np.random.PCG64(11))
+    X, Y, Z = _grid(N, L)
+    zg = np.zeros((N, N, N))
+    for _ in range(6):
+        n = rs.integers(-2, 3, size=3)
+        zg += rs.normal() * np.cos(n[0] * X + n[1] * Y + n[2] * Z + rs.uniform(0, 2 * math.pi))
+    for F in (zg, zg * zg):
+        lap = field.laplacian(F, L)
+        fd = _fd4_laplacian(F, h)
+        assert np.max(np.abs(lap - fd)) <= 2e-3 * np.max(np.abs(lap))
+    lhs = float(np.mean(zg * field.laplacian(zg, L)))
+    rhs = -float(np.mean(_fd4_grad2(zg, h)))
+    assert abs(lhs - rhs) <= 2e-3 * abs(rhs)
+    # the map itself is the stated combination of the two
+    m = W.NGMap("nonlocal", alpha_NL=0.4, beta_NL=0.9, k_NL=2.0)
+    got = field.apply_map(zg, m, L)
+    ref = zg + 0.4 / 4.0 * _fd4_laplacian(zg * zg, h) + 0.9 / 4.0 * zg * _fd4_laplacian(zg, h)
+    assert np.max(np.abs(got - ref)) <= 2e-3 * np.max(np.abs(got - zg))

@@ -24,6 +24,7 @@ TWO_PI = 2.0 * math.pi
 MAP_GAUSS = "gauss"
 MAP_LOCAL = "local"
 MAP_EXPTAIL = "exptail"
+MAP_NONLOCAL = "nonlocal"
 
 
 @dataclass(frozen=True)
@@ -44,12 +45,18 @@ class NGMap:
                       (Sec. VI B; <zeta_g^2> is the FP64 sample mean over the
                       lattice, which only moves the k = 0 mode)
     kind = "exptail": zeta = -ln(max(1 - beta zeta_g, clip)) / beta
+    kind = "nonlocal": zeta = zeta_g + (alpha_NL / k_NL^2) lap(zeta_g^2)
+                              + (beta_NL / k_NL^2) zeta_g lap(zeta_g)
+                      (Eq. nonlocal; k_NL is the peak scale k* of the spectrum)
     """
     kind: str = MAP_GAUSS
     F_NL: float = 0.0
     G_NL: float = 0.0
     beta: float = 0.0
     clip: float = 1e-6
+    alpha_NL: float = 0.0
+    beta_NL: float = 0.0
+    k_NL: float = 0.0
 
 
 @dataclass(frozen=True)
