@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum { SIGW_F32 = 0, SIGW_F64 = 1 } sigw_prec;
 
-typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2 } sigw_map_kind;
+typedef enum { SIGW_MAP_GAUSS = 0, SIGW_MAP_LOCAL = 1, SIGW_MAP_EXPTAIL = 2, SIGW_MAP_NONLOCAL = 3 } sigw_map_kind;
 
 /* Plan description: the lattice and the separable decomposition of Sec. V.
  * N must be one of 8, 16, 32, 64, 128, 256, 384, 512 (2^a 3^b sizes with a
@@ -98,12 +98,17 @@ typedef struct {
  * The field's spectrum is P(k) = 2 pi^2 Delta^2(k) / k^3.  A >= 0, sigma > 0, k_star > 0. */
 typedef struct { double A, sigma, k_star; } sigw_lognormal;
 
-/* Non-Gaussian map (Sec. VI B and the exponential-tail family):
- *   GAUSS:   zeta = zeta_g
- *   LOCAL:   zeta = zeta_g + F_NL (zeta_g^2 - <zeta_g^2>) + G_NL zeta_g^3,
- *            <zeta_g^2> the FP64 mean over the lattice
- *   EXPTAIL: zeta = -ln(max(1 - beta zeta_g, clip)) / beta, beta > 0, clip > 0 */
-typedef struct { int32_t kind; double F_NL, G_NL, beta, clip; } sigw_ngmap;
+/* Non-Gaussian map (Sec. VI B, Sec. VI C and the exponential-tail family):
+ *   GAUSS:    zeta = zeta_g
+ *   LOCAL:    zeta = zeta_g + F_NL (zeta_g^2 - <zeta_g^2>) + G_NL zeta_g^3,
+ *             <zeta_g^2> the FP64 mean over the lattice
+ *   EXPTAIL:  zeta = -ln(max(1 - beta zeta_g, clip)) / beta, beta > 0, clip > 0
+ *   NONLOCAL: zeta = zeta_g + (alpha_NL / k_NL^2) lap(zeta_g^2)
+ *                    + (beta_NL / k_NL^2) zeta_g lap(zeta_g)      (Eq. nonlocal)
+ *             with the spectral Laplacian lap X = IDFT(-|k_F n|^2 DFT X) (the
+ *             Nyquist index keeps its value); k_NL > 0 is the peak scale.
+ *             Uses the plan's gradient-field workspace as scratch. */
+typedef struct { int32_t kind; double F_NL, G_NL, beta, clip, alpha_NL, beta_NL, k_NL; } sigw_ngmap;
 
 /* Fill d with the paper's default decomposition (n_modes 200, n_alpha 50,
  * u in [1e-3, 15), u_p 1, sigma_p 0.5, A_p 10), one slot, all terms per

@@ -22,7 +22,7 @@ SIGW_E_PENDING = -6
 SIGW_F32 = 0
 SIGW_F64 = 1
 
-MAP_KINDS = {"gauss": 0, "local": 1, "exptail": 2}
+MAP_KINDS = {"gauss": 0, "local": 1, "exptail": 2, "nonlocal": 3}
 
 # every entry point the header declares
 EXPORTS = (
@@ -54,7 +54,8 @@ class Lognormal(ct.Structure):
 
 class NGMap(ct.Structure):
     _fields_ = [("kind", ct.c_int32), ("F_NL", ct.c_double), ("G_NL", ct.c_double),
-                ("beta", ct.c_double), ("clip", ct.c_double)]
+                ("beta", ct.c_double), ("clip", ct.c_double), ("alpha_NL", ct.c_double),
+                ("beta_NL", ct.c_double), ("k_NL", ct.c_double)]
 
 
 class SigwError(RuntimeError):

@@ -80,6 +80,8 @@ def ngmap_struct(m) -> _lib.NGMap:
     s.kind = _lib.MAP_KINDS[m.kind] if isinstance(m.kind, str) else int(m.kind)
     s.F_NL, s.G_NL = float(getattr(m, "F_NL", 0.0)), float(getattr(m, "G_NL", 0.0))
     s.beta, s.clip = float(getattr(m, "beta", 0.0)), float(getattr(m, "clip", 1e-6))
+    s.alpha_NL, s.beta_NL = float(getattr(m, "alpha_NL", 0.0)), float(getattr(m, "beta_NL", 0.0))
+    s.k_NL = float(getattr(m, "k_NL", 0.0))
     return s
 
 

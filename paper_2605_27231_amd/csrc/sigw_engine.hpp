@@ -44,6 +44,12 @@ struct Engine {
     // real_out = scale * map(real_in), evaluated in FP64; m2 = <zeta_g^2> on the device.
     virtual void map_scale(const void* real_in, void* real_out, const double* sum_sq,
                            const MapParams& mp, double scale, hipStream_t s) = 0;
+    // Non-local map pieces: half *= c |n|^2 (spectral Laplacian with c =
+    // -k_F^2 times any coefficient and normalisation, evaluated in FP64);
+    // out = in^2; out = zg + l1 + zg l2 (FP64 per site).
+    virtual void laplacian(void* half, double c, hipStream_t s) = 0;
+    virtual void square(const void* in, void* out, hipStream_t s) = 0;
+    virtual void nonlocal_combine(const void* zg, const void* l1, const void* l2, void* out, hipStream_t s) = 0;
     // Per-target tables over integer |n|^2 in [0, 3 (N/2)^2]: u-interval index
     // of u = k_F sqrt(n2) / k_target (-1 outside) and shell membership
     // k_lo <= k_F sqrt(n2) < k_hi, n2 > 0.

@@ -388,6 +388,42 @@ __global__ __launch_bounds__(256) void k_filter(typename CplxOf<R>::T* __restric
     half[i] = cmk<C>(v.x * a, v.y * a);
 }
 
+// Spectral Laplacian of a half spectrum, times a constant: X(n) *= c |n|^2.
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_laplacian(typename CplxOf<R>::T* __restrict__ half, double c) {
+    using C = typename CplxOf<R>::T;
+    constexpr long FS = Shape<R, N>::FS;
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= FS) return;
+    const int kz = int(i % N);
+    const int ky = int((i / N) % N);
+    const int kx = int(i / (long(N) * N));
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
+    const R a = (R)(c * double(nx * nx + ny * ny + nz * nz));
+    C v = half[i];
+    half[i] = cmk<C>(v.x * a, v.y * a);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_square(const R* __restrict__ in, R* __restrict__ out, long total) {
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= total) return;
+    const double v = (double)in[i];
+    out[i] = (R)(v * v);
+}
+
+// zeta = zeta_g + l1 + zeta_g l2 (the two Laplacian terms of the non-local
+// map, their coefficients already applied), in FP64
+template <typename R>
+__global__ __launch_bounds__(256) void k_nonlocal_combine(const R* __restrict__ zg, const R* __restrict__ l1,
+                                                          const R* __restrict__ l2, R* __restrict__ out,
+                                                          long total) {
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= total) return;
+    const double z = (double)zg[i];
+    out[i] = (R)(z + (double)l1[i] + z * (double)l2[i]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_sumsq_partial(const R* __restrict__ x, long total, double* __restrict__ part) {
     __shared__ double red[256];
@@ -1132,6 +1168,20 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     }
     void filter(void* half, const double* amp, hipStream_t s) override {
         k_filter<R, NN><<<dim3(unsigned((S::FS + 255) / 256)), dim3(256), 0, s>>>(static_cast<C*>(half), amp);
+    }
+    void laplacian(void* half, double c, hipStream_t s) override {
+        k_laplacian<R, NN><<<dim3(unsigned((S::FS + 255) / 256)), dim3(256), 0, s>>>(static_cast<C*>(half), c);
+    }
+    void square(const void* in, void* out, hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_square<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(static_cast<const R*>(in),
+                                                                           static_cast<R*>(out), total);
+    }
+    void nonlocal_combine(const void* zg, const void* l1, const void* l2, void* out, hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_nonlocal_combine<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(
+            static_cast<const R*>(zg), static_cast<const R*>(l1), static_cast<const R*>(l2), static_cast<R*>(out),
+            total);
     }
     void sumsq(const void* real, double* partials, double* out, hipStream_t s) override {
         const long total = long(NN) * NN * NN;

@@ -826,7 +826,9 @@ sigw_status sigw_generate_field(sigw_plan_t p, int32_t slot, uint64_t seed, cons
     if (sigw_status s = check_slot(p, slot, false)) return s;
     if (!(sp->A >= 0.0) || !finite_pos(sp->sigma) || !finite_pos(sp->k_star) || !std::isfinite(sp->A))
         return fail(p, SIGW_E_INVALID, "log-normal needs A >= 0, sigma > 0, k_star > 0");
-    if (mp->kind < 0 || mp->kind > 2) return fail(p, SIGW_E_INVALID, "unknown map kind");
+    if (mp->kind < 0 || mp->kind > 3) return fail(p, SIGW_E_INVALID, "unknown map kind");
+    if (mp->kind == 3 && (!finite_pos(mp->k_NL) || !std::isfinite(mp->alpha_NL) || !std::isfinite(mp->beta_NL)))
+        return fail(p, SIGW_E_INVALID, "non-local map needs finite alpha_NL, beta_NL and k_NL > 0");
     if (mp->kind == 2 && (!finite_pos(mp->beta) || !finite_pos(mp->clip)))
         return fail(p, SIGW_E_INVALID, "exponential tail needs beta > 0 and clip > 0");
     if (mp->kind == 1 && (!std::isfinite(mp->F_NL) || !std::isfinite(mp->G_NL)))
@@ -861,11 +863,36 @@ sigw_status sigw_generate_field(sigw_plan_t p, int32_t slot, uint64_t seed, cons
     p->eng->ypass(half, 1, z.FS, int(z.H), -1, 1, 0, p->stream);
     p->eng->zpass(half, z.H * d.N, -1, p->stream);
     p->eng->filter(half, p->amp, p->stream);
-    p->eng->zpass(half, z.H * d.N, +1, p->stream);
-    p->eng->ypass(half, 1, z.FS, int(z.H), +1, 1, 0, p->stream);
-    p->eng->xpass_c2r(half, p->real, p->stream);
-    sigw::MapParams m{mp->kind, mp->F_NL, mp->G_NL, mp->beta, mp->clip};
-    return finish_field(p, slot, m, mp->kind == 1);
+    auto c2r = [&](void* h, void* real_out) {
+        p->eng->zpass(h, z.H * d.N, +1, p->stream);
+        p->eng->ypass(h, 1, z.FS, int(z.H), +1, 1, 0, p->stream);
+        p->eng->xpass_c2r(h, real_out, p->stream);
+    };
+    if (mp->kind != 3) {
+        c2r(half, p->real);
+        sigw::MapParams m{mp->kind, mp->F_NL, mp->G_NL, mp->beta, mp->clip};
+        return finish_field(p, slot, m, mp->kind == 1);
+    }
+    // Eq. nonlocal, in the gradient-field workspace: hl (half spectrum),
+    // l2 = (beta_NL/k_NL^2) lap zeta_g, l1 = (alpha_NL/k_NL^2) lap(zeta_g^2)
+    void* hl = p->T;
+    void* l2 = cplx_at(p->T, z.FS, z.cb);
+    void* l1 = cplx_at(p->T, 2 * z.FS, z.cb);
+    const double c_nl = -kF * kF / (mp->k_NL * mp->k_NL);
+    HIP_TRY(p, hipMemcpyAsync(hl, half, size_t(z.FS) * z.cb, hipMemcpyDeviceToDevice, p->stream));
+    p->eng->laplacian(hl, mp->beta_NL * c_nl, p->stream);
+    c2r(hl, l2);
+    c2r(half, p->real);                                    // zeta_g
+    p->eng->square(p->real, l1, p->stream);
+    p->eng->xpass_r2c(l1, hl, p->stream);
+    p->eng->ypass(hl, 1, z.FS, int(z.H), -1, 1, 0, p->stream);
+    p->eng->zpass(hl, z.H * d.N, -1, p->stream);
+    // the forward and inverse passes are unnormalised: divide by N^3
+    p->eng->laplacian(hl, mp->alpha_NL * c_nl / double(z.R3), p->stream);
+    c2r(hl, l1);
+    p->eng->nonlocal_combine(p->real, l1, l2, p->real, p->stream);
+    sigw::MapParams m{0, 0.0, 0.0, 0.0, 0.0};
+    return finish_field(p, slot, m, false);
 }
 
 sigw_status sigw_set_zeta(sigw_plan_t p, int32_t slot, const void* zeta_dev) {

@@ -73,14 +73,18 @@ def test_phi_hat_from_zeta(N, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("ngmap", [W.NGMap("gauss"), W.NGMap("local", F_NL=3.0, G_NL=1.0),
-                                   W.NGMap("exptail", beta=3.0, clip=1e-6)], ids=["gauss", "local", "exptail"])
-def test_generate_field(prec, ngmap):
-    N, L = 64, 2 * math.pi
+@pytest.mark.parametrize("ngmap,L", [
+    (W.NGMap("gauss"), 2 * math.pi), (W.NGMap("local", F_NL=3.0, G_NL=1.0), 2 * math.pi),
+    (W.NGMap("exptail", beta=3.0, clip=1e-6), 2 * math.pi),
+    (W.NGMap("nonlocal", alpha_NL=2.0, beta_NL=-3.0, k_NL=6.0), 2 * math.pi),
+    (W.NGMap("nonlocal", alpha_NL=-1.5, beta_NL=2.5, k_NL=4.0), 3 * math.pi)],
+    ids=["gauss", "local", "exptail", "nonlocal", "nonlocal-L3pi"])
+def test_generate_field(prec, ngmap, L):
+    N = 64
     spec = W.Lognormal(1e-2, 0.5, 6.0)
     _say(f"generate N={N} prec={prec} map={ngmap.kind}")
     ref = field.phi_hat(N, L, 3, spec, ngmap)
-    with P.Plan(N, prec=prec) as pl:
+    with P.Plan(N, L=L, prec=prec) as pl:
         pl.generate_field(0, 3, spec, ngmap)
         got = _np(pl.get_phi_hat(0)).astype(np.complex128)
     tol = 1e-11 if prec == "f64" else 2e-5
@@ -135,8 +139,9 @@ def test_spectrum_plain_fp64_32cube(tabs):
     _say("max rel err per bin", rel.max())
 
 
-@pytest.mark.parametrize("ngmap", [W.NGMap("local", F_NL=3.0), W.NGMap("exptail", beta=3.0)],
-                         ids=["local", "exptail"])
+@pytest.mark.parametrize("ngmap", [W.NGMap("local", F_NL=3.0), W.NGMap("exptail", beta=3.0),
+                                   W.NGMap("nonlocal", alpha_NL=2.0, beta_NL=-3.0, k_NL=8.0)],
+                         ids=["local", "exptail", "nonlocal"])
 def test_spectrum_fp32_vs_fp64_oracle(tabs, ngmap):
     """FP32 fields/FFTs with FP64 shell sums against the FP64 oracle: 1e-4 per bin."""
     N, L = 64, 2 * math.pi
@@ -187,6 +192,9 @@ def test_errors_and_state():
         assert e.value.status == -1        # k_lo >= k_hi
         with pytest.raises(P.SigwError) as e:
             pl.generate_field(0, 0, W.Lognormal(1e-2, -0.5, 3.0), W.NGMap())
+        assert e.value.status == -1
+        with pytest.raises(P.SigwError) as e:       # the non-local map needs k_NL > 0
+            pl.generate_field(0, 0, W.Lognormal(1e-2, 0.5, 3.0), W.NGMap("nonlocal", alpha_NL=1.0))
         assert e.value.status == -1
         om, nb = pl.spectrum(1, [2.0], [1.5], [2.5])
         assert nb[0] > 0 and om[0] > 0
