@@ -201,3 +201,95 @@ def test_map_properties(tabs):
     lc = om(field.apply_map(small, W.NGMap("local", F_NL=beta / 2, G_NL=beta ** 2 / 3)))
     assert np.all(np.abs(ex - g) > 1e-4 * g)            # the non-Gaussian part is visible
     np.testing.assert_allclose(ex - g, lc - g, rtol=2e-3)
+
+
+# --------------------------------------------------------------- jackknife
+from oracle import jackknife  # noqa: E402
+
+
+def _random_hermitian_qhat(N, seed):
+    """Six half spectra that are DFTs of real fields (so Hermitian)."""
+    rs = np.random.Generator(np.random.PCG64(seed))
+    return np.stack([lattice.forward(rs.normal(size=(N, N, N)), 2 * np.pi) for _ in range(6)])
+
+
+def test_jackknife_sums_reproduce_shell_sum():
+    """Parseval: the sub-volume sums of the real-space TT fields add up to the
+    shell estimator's S_b (computed mode by mode), and the replica mean is Omega."""
+    N, L, M = 16, 2 * np.pi, 4
+    Qs, Qc = _random_hermitian_qhat(N, 1), _random_hermitian_qhat(N, 2)
+    for k_b, lo, hi in ((3.0, 2.5, 3.5), (5.2, 4.6, 5.9)):
+        h = jackknife.shell_tt_fields(Qs, Qc, k_b, lo, hi, L)
+        S_i = jackknife.subvolume_sums(h, L, M)
+        S_b, N_b = spectrum.shell_sum(Qs, Qc, k_b, lo, hi, L)
+        assert abs(S_i.sum() - S_b) <= 1e-12 * S_b
+        om, sigma, rep = jackknife.jackknife_from_sums(S_i, N_b, k_b, L)
+        assert abs(rep.mean() - om) <= 1e-12 * om and sigma > 0
+        assert abs(om - spectrum.omega_from_sum(S_b, N_b, k_b, L)) <= 1e-12 * om
+
+
+def test_jackknife_fields_by_direct_sum():
+    """The real-space fields against an explicit sum over the shell's full-grid
+    modes with the projector built from the explicit e^+, e^x tensors' sum
+    (sum_lambda e^lambda_ij e^lambda_lm = Lambda_ij,lm) on 8^3."""
+    N, L = 8, 2 * np.pi
+    Qs, Qc = _random_hermitian_qhat(N, 3), _random_hermitian_qhat(N, 4)
+    k_b, lo, hi = 2.4, 2.0, 3.0
+    h = jackknife.shell_tt_fields(Qs, Qc, k_b, lo, hi, L)
+    x = np.arange(N) * (L / N)
+    X_, Y_, Z_ = np.meshgrid(x, x, x, indexing="ij")
+    nx, ny, nz = lattice.mode_grids_full(N)
+    ref = np.zeros((2, 3, 3, N, N, N), dtype=np.complex128)
+    for m, (Q, sign) in enumerate(((Qs, -1.0), (Qc, 1.0))):
+        for a in range(N):
+            for b in range(N):
+                for c in range(N):
+                    n = np.array([nx[a, 0, 0], ny[0, b, 0], nz[0, 0, c]], dtype=np.float64)
+                    kk = np.linalg.norm(n)
+                    if kk == 0 or not (lo <= kk < hi):
+                        continue
+                    # X(n) from the half layout (conjugate for kx < 0)
+                    if n[0] >= 0 and a <= N // 2:
+                        Xc = Q[:, a, b, c]
+                    else:
+                        Xc = np.conj(Q[:, (-a) % N, (-b) % N, (-c) % N])
+                    T = np.zeros((3, 3), dtype=np.complex128)
+                    for cc, (i, j) in enumerate(spectrum.PAIRS):
+                        T[i, j] = T[j, i] = sign * 4.0 / k_b ** 2 * Xc[cc]
+                    kh = n / kk
+                    Pm = np.eye(3) - np.outer(kh, kh)
+                    Lam = 0.5 * (np.einsum("il,jm->ijlm", Pm, Pm) + np.einsum("im,jl->ijlm", Pm, Pm)
+                                 - np.einsum("ij,lm->ijlm", Pm, Pm))
+                    Yt = np.einsum("ijlm,lm->ij", Lam, T)
+                    ph = np.exp(1j * (n[0] * X_ + n[1] * Y_ + n[2] * Z_))
+                    ref[m] += Yt[:, :, None, None, None] * ph[None, None] / L ** 3
+    assert np.max(np.abs(ref.imag)) <= 1e-12 * np.max(np.abs(ref.real))
+    assert np.max(np.abs(h - ref.real)) <= 1e-12 * np.max(np.abs(h))
+
+
+def test_jackknife_single_commensurate_mode_has_zero_error():
+    """One mode pair +-n whose wavelength divides the sub-volume edge: every
+    sub-volume holds the same energy, so every replica equals Omega and the
+    jackknife error vanishes; a second, incommensurate mode breaks that."""
+    N, L, M = 16, 2 * np.pi, 2
+    Q = np.zeros((6, N // 2 + 1, N, N), dtype=np.complex128)
+    Q[:, 0, 2, 0] = [1.0, 0.5, -0.3, 0.2j, 0.1, -0.4j]          # n = (0, 2, 0): wavelength N/2
+    Q[:, 0, N - 2, 0] = np.conj(Q[:, 0, 2, 0])                    # its mirror in the kx = 0 plane
+    Z = np.zeros_like(Q)
+    h = jackknife.shell_tt_fields(Q, Z, 2.0, 1.5, 2.5, L)
+    om, sigma, rep = jackknife.jackknife_from_sums(jackknife.subvolume_sums(h, L, M), 2, 2.0, L)
+    assert om > 0 and sigma <= 1e-12 * om
+    # two modes n = (1, 0, 0) and (0, 1, 0) of one shell: their interference
+    # cos(2 pi (x - y) / N) puts different energy into different sub-volumes
+    Q2 = np.zeros_like(Q)
+    Q2[:, 1, 0, 0] = [0.3, 0.2, 0.5, 0.0, 0.05, 0.1]
+    Q2[:, 0, 1, 0] = [0.2, 0.1, 0.4, 0.0, 0.1, 0.0]
+    Q2[:, 0, N - 1, 0] = np.conj(Q2[:, 0, 1, 0])
+    h = jackknife.shell_tt_fields(Q2, Z, 1.0, 0.5, 1.5, L)
+    S_i = jackknife.subvolume_sums(h, L, M)
+    om, sigma, rep = jackknife.jackknife_from_sums(S_i, 4, 1.0, L)
+    assert sigma > 1e-3 * om and np.ptp(S_i) > 1e-3 * S_i.mean()
+    with pytest.raises(ValueError):
+        jackknife.subvolume_sums(h, L, 3)
+    with pytest.raises(ValueError):
+        jackknife.shell_tt_fields(Q, Z, 8.0, 7.5, 8.5, L)
