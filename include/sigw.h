@@ -186,6 +186,22 @@ sigw_status sigw_spectrum_batch(sigw_plan_t plan, int32_t n_sel, const int32_t* 
                                 int32_t n_k, const double* k_targets, const double* k_lo,
                                 const double* k_hi, double* omega_host, int64_t* nmodes_host);
 
+/* Spectrum of one slot with jackknife error bars (Sec. IV): for every target,
+ * Omega and N_b as sigw_spectrum, and the error of Omega from M^3
+ * leave-one-out replicas.  The TT-projected modes of the shell (both
+ * kernels) are transformed to real space; by Parseval the shell power splits
+ * into the M^3 sub-volume sums S_i (FP64); replica i takes
+ * M^3/(M^3-1) (S_b - S_i) with the shell's N_b, and
+ * omega_err = sqrt((M^3-1)/M^3 sum_i (Omega_i - mean)^2).  M >= 2 divides N
+ * and M^3 < 4096 (the paper uses M = 4); every shell must lie below the
+ * Nyquist frequency k_F N/2.  replicas (n_k * M^3, may be NULL) receives
+ * the replica Omegas, sub-volume index (a M + b) M + c for x in
+ * [a, a+1) N/M, y in [b, b+1) N/M, z in [c, c+1) N/M.  Uses the plan's
+ * workspace; synchronises the plan stream after every target. */
+sigw_status sigw_spectrum_jackknife(sigw_plan_t plan, int32_t slot, int32_t n_k, const double* k_targets,
+                                    const double* k_lo, const double* k_hi, int32_t M, double* omega_host,
+                                    int64_t* nmodes_host, double* omega_err_host, double* replicas_host);
+
 /* Asynchronous form for serving loops: enqueue the spectrum of one slot
  * (n_k <= 64) and return at once; sigw_spectrum_poll returns SIGW_E_PENDING
  * until the plan stream has finished that work, then writes the results as

@@ -32,7 +32,7 @@ EXPORTS = (
     "sigw_spectrum_batch", "sigw_spectrum_enqueue", "sigw_spectrum_poll", "sigw_synchronize",
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
-    "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule",
+    "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -105,6 +105,7 @@ def lib() -> ct.CDLL:
         "sigw_graph_results": [P, D, I64],
         "sigw_graph_destroy": [P],
         "sigw_autotune": [P, ct.c_int32],
+        "sigw_spectrum_jackknife": [P, ct.c_int32, ct.c_int32, D, D, D, ct.c_int32, D, I64, D, D],
         "sigw_plan_schedule": [P, I32, I32, ct.c_char_p, ct.c_size_t],
         "sigw_plan_set_schedule": [P, ct.c_int32],
     }

@@ -183,6 +183,20 @@ class Plan:
         self._chk(st, "sigw_spectrum_batch")
         return om, nb
 
+    def spectrum_jackknife(self, slot: int, targets, k_lo, k_hi, M: int = 4):
+        """(omega, nmodes, omega_err, replicas[n_k, M^3]) with jackknife errors."""
+        t = np.ascontiguousarray(targets, dtype=np.float64)
+        lo = np.ascontiguousarray(k_lo, dtype=np.float64)
+        hi = np.ascontiguousarray(k_hi, dtype=np.float64)
+        n = len(t)
+        om, err = np.zeros(n), np.zeros(n)
+        nb = np.zeros(n, dtype=np.int64)
+        rep = np.zeros((n, M ** 3))
+        st = lib().sigw_spectrum_jackknife(self.h, slot, n, _dptr(t), _dptr(lo), _dptr(hi), int(M), _dptr(om),
+                                           _i64ptr(nb), _dptr(err), _dptr(rep))
+        self._chk(st, "sigw_spectrum_jackknife")
+        return om, nb, err, rep
+
     def spectrum_enqueue(self, slot: int, targets, k_lo, k_hi):
         self._pend = (np.ascontiguousarray(targets, dtype=np.float64),
                       np.ascontiguousarray(k_lo, dtype=np.float64),

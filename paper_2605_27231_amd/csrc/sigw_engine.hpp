@@ -89,6 +89,13 @@ struct Engine {
     virtual void zbin(const void* Qxy, int nb, long q_stride, const uint8_t* lut_shell, int n2_lo,
                       int n2_hi, double* partial_sum, unsigned long long* partial_cnt,
                       hipStream_t s) = 0;
+    // Jackknife support (one realisation): forward z pass of the 12
+    // components + TT projection of the shell's modes written back in place,
+    // everything else zeroed; E = (first ? 0 : E) + w h^2 per site in FP64;
+    // the sums of E over the M^3 sub-volumes.
+    virtual void ztt(void* Q, const uint8_t* lut_shell, int n2_lo, int n2_hi, hipStream_t s) = 0;
+    virtual void energy_accum(const void* h, double* E, double w, int first, hipStream_t s) = 0;
+    virtual void subvol_sums(const double* E, int M, double* out, hipStream_t s) = 0;
     // Fixed-order reduction of each member's n partials into
     // out_sum[b * out_stride], out_cnt[b * out_stride].
     virtual void finalize(const double* partial_sum, const unsigned long long* partial_cnt, int n, int nb,

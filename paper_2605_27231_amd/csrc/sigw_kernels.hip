@@ -1088,6 +1088,153 @@ __global__ __launch_bounds__(256) void k_zbin(const typename CplxOf<R>::T* __res
     }
 }
 
+// Lambda(X) = P X P - 1/2 P tr(P X P) of a symmetric X (6 comps xx, yy, zz,
+// xy, xz, yz), P = 1 - k k^T: the TT projection whose squared norm tt_power
+// returns.
+__device__ __forceinline__ void tt_project(const double2* X, double kx, double ky, double kz, double2* Y6) {
+    const double k[3] = {kx, ky, kz};
+    double2 M[3][3];
+    M[0][0] = X[0]; M[1][1] = X[1]; M[2][2] = X[2];
+    M[0][1] = M[1][0] = X[3];
+    M[0][2] = M[2][0] = X[4];
+    M[1][2] = M[2][1] = X[5];
+    double2 a[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        a[i].x = M[i][0].x * k[0] + M[i][1].x * k[1] + M[i][2].x * k[2];
+        a[i].y = M[i][0].y * k[0] + M[i][1].y * k[1] + M[i][2].y * k[2];
+    }
+    double2 beta;
+    beta.x = k[0] * a[0].x + k[1] * a[1].x + k[2] * a[2].x;
+    beta.y = k[0] * a[0].y + k[1] * a[1].y + k[2] * a[2].y;
+    double2 Y[3][3];
+    double2 tr;
+    tr.x = 0.0;
+    tr.y = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Y[i][j].x = M[i][j].x - k[i] * a[j].x - a[i].x * k[j] + beta.x * k[i] * k[j];
+            Y[i][j].y = M[i][j].y - k[i] * a[j].y - a[i].y * k[j] + beta.y * k[i] * k[j];
+            if (i == j) {
+                tr.x += Y[i][j].x;
+                tr.y += Y[i][j].y;
+            }
+        }
+    const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int i = ci[c], j = cj[c];
+        const double pij = (i == j ? 1.0 : 0.0) - k[i] * k[j];
+        Y6[c].x = Y[i][j].x - 0.5 * pij * tr.x;
+        Y6[c].y = Y[i][j].y - 0.5 * pij * tr.y;
+    }
+}
+
+// Jackknife support: the last forward pass (z) of the 12 components, then
+// the TT projection of the shell's modes written back in place (frequency
+// space); every other mode is zeroed, including rows that cannot reach the
+// shell, so that the inverse transforms that follow see only the shell.
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_ztt(typename CplxOf<R>::T* __restrict__ Q, const uint8_t* __restrict__ lut_shell,
+                                             int n2_lo, int n2_hi, const typename CplxOf<R>::T* __restrict__ tw) {
+    using C = typename CplxOf<R>::T;
+    constexpr int RB = Shape<R, N>::RBB_;
+    constexpr long FS = Shape<R, N>::FS;
+    constexpr int NT = 256;
+    constexpr int NL = 12 * RB;
+    constexpr int LS = N;
+    constexpr int BUF = CMax<TPLayout<N, NL, false>::size, NL * LS>::v;
+    __shared__ C buf[BUF];
+    const int tid = threadIdx.x;
+    const long row0 = long(blockIdx.x) * RB;
+    bool any = false;
+    for (int r = 0; r < RB; ++r) {
+        const long rr = row0 + r;
+        const int kx = int(rr / N), ky = int(rr % N);
+        const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+        const int mn = nx * nx + ny * ny;
+        const int mx = mn + (N / 2) * (N / 2);
+        if (mn <= n2_hi && mx >= n2_lo) any = true;
+    }
+    if (!any) {
+        for (int e = tid; e < 12 * RB * N; e += NT) {
+            const int comp = e / (RB * N), rem = e % (RB * N);
+            Q[long(comp) * FS + row0 * N + rem] = cmk<C>(R(0), R(0));
+        }
+        return;
+    }
+    auto ld = [&](int line, int kz) -> C {
+        const int comp = line / RB, row = line % RB;
+        return Q[long(comp) * FS + (row0 + row) * N + kz];
+    };
+    tp_phase1<C, N, -1, NL, NT, false>(ld, buf, tw, tid);
+    __syncthreads();
+    TPRegs<C, N, -1, NL, NT, false> f;
+    f.run(buf, tid);
+    __syncthreads();
+    f.store([&](int line, int kz, C v) { buf[line * LS + kz] = v; }, tid);
+    __syncthreads();
+    for (int e = tid; e < RB * N; e += NT) {
+        const int row = e / N, kz = e % N;
+        const long rr = row0 + row;
+        const int kx = int(rr / N), ky = int(rr % N);
+        const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = signed_index(kz, N);
+        const int n2 = nx * nx + ny * ny + nz * nz;
+        const bool in = n2 >= n2_lo && n2 <= n2_hi && lut_shell[n2];
+        const double inv = in ? 1.0 / sqrt((double)n2) : 0.0;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            double2 X[6], Y[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const C v = buf[((m * 6 + c) * RB + row) * LS + kz];
+                X[c].x = (double)v.x;
+                X[c].y = (double)v.y;
+            }
+            tt_project(X, nx * inv, ny * inv, nz * inv, Y);
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                Q[long(m * 6 + c) * FS + rr * N + kz] = in ? cmk<C>((R)Y[c].x, (R)Y[c].y) : cmk<C>(R(0), R(0));
+        }
+    }
+}
+
+// E[x] = (first ? 0 : E[x]) + w h[x]^2, in FP64
+template <typename R>
+__global__ __launch_bounds__(256) void k_energy_accum(const R* __restrict__ h, double* __restrict__ E, long total,
+                                                      double w, int first) {
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= total) return;
+    const double v = (double)h[i];
+    E[i] = (first ? 0.0 : E[i]) + w * v * v;
+}
+
+// out[(a M + b) M + c] = sum of E over the sub-volume x in [a, a+1) N/M,
+// y in [b, b+1) N/M, z in [c, c+1) N/M; one block per sub-volume, fixed-order
+// reduction.
+__global__ __launch_bounds__(256) void k_subvol_sums(const double* __restrict__ E, int N, int M,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    const int sv = blockIdx.x;
+    const int a = sv / (M * M), b = (sv / M) % M, c = sv % M;
+    const int B = N / M;
+    const long nsite = long(B) * B * B;
+    double acc = 0.0;
+    for (long t = threadIdx.x; t < nsite; t += 256) {
+        const int z = int(t % B), y = int((t / B) % B), x = int(t / (long(B) * B));
+        acc += E[(long(a * B + x) * N + (b * B + y)) * N + (c * B + z)];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[sv] = red[0];
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ ps_all,
                                                   const unsigned long long* __restrict__ pc_all, int n,
                                                   double* __restrict__ out_sum, unsigned long long* __restrict__ out_cnt,
@@ -1261,6 +1408,18 @@ template <typename R, int NN> struct EngineImpl final : Engine {
               unsigned long long* pc, hipStream_t s) override {
         k_zbin<R, NN><<<dim3(unsigned(zbin_blocks()), unsigned(nb)), dim3(256), 0, s>>>(
             static_cast<const C*>(Qxy), q_stride, lut_shell, n2_lo, n2_hi, ps, pc, tw);
+    }
+    void ztt(void* Q, const uint8_t* lut_shell, int n2_lo, int n2_hi, hipStream_t s) override {
+        k_ztt<R, NN><<<dim3(unsigned(zbin_blocks())), dim3(256), 0, s>>>(static_cast<C*>(Q), lut_shell, n2_lo, n2_hi,
+                                                                         tw);
+    }
+    void energy_accum(const void* h, double* E, double w, int first, hipStream_t s) override {
+        const long total = long(NN) * NN * NN;
+        k_energy_accum<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(static_cast<const R*>(h), E,
+                                                                                   total, w, first);
+    }
+    void subvol_sums(const double* E, int M, double* out, hipStream_t s) override {
+        k_subvol_sums<<<dim3(unsigned(M * M * M)), dim3(256), 0, s>>>(E, NN, M, out);
     }
     void finalize(const double* ps, const unsigned long long* pc, int n, int nb, double* out_sum,
                   unsigned long long* out_cnt, int out_stride, hipStream_t s) override {

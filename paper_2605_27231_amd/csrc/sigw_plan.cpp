@@ -961,6 +961,82 @@ sigw_status sigw_spectrum_batch(sigw_plan_t p, int32_t n_sel, const int32_t* slo
     return SIGW_OK;
 }
 
+sigw_status sigw_spectrum_jackknife(sigw_plan_t p, int32_t slot, int32_t n_k, const double* kt, const double* lo,
+                                    const double* hi, int32_t M, double* omega, int64_t* nmodes, double* omega_err,
+                                    double* replicas) {
+    if (!p) return SIGW_E_INVALID;
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
+    if (sigw_status s = check_slot(p, slot, true)) return s;
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    const long M3 = long(M) * M * M;
+    if (M < 2 || d.N % M != 0 || M3 >= kMaxTargets || M3 > z.H * d.N)
+        return fail(p, SIGW_E_INVALID, "M must be >= 2, divide N, and M^3 stay below 4096");
+    const double kF = 2.0 * kPi / d.L;
+    for (int b = 0; b < n_k; ++b)
+        if (hi[b] > kF * (d.N / 2)) return fail(p, SIGW_E_INVALID, "jackknife shells must lie below k_F N/2");
+    // E (one FP64 value per site) lives in the gradient-field workspace,
+    // which is free once the x pass of a target has run
+    double* E = static_cast<double*>(p->T);
+    const double wcomp[6] = {1.0, 1.0, 1.0, 2.0, 2.0, 2.0};   // off-diagonal components stand for two
+    if (sigw_status s = upload_sel(p, &slot, 1)) return s;
+    for (int b = 0; b < n_k; ++b) {
+        std::vector<int> valid;
+        if (sigw_status s = enqueue_spectrum(p, p->d_sel, 1, 1, kt + b, lo + b, hi + b, p->sums, p->cnts, valid))
+            return s;
+        double* S_i = p->part_sum;     // after finalize has consumed the zbin partials
+        if (valid[0]) {
+            int n2_lo = 0, n2_hi = -1;
+            shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi);
+            p->eng->ztt(p->Q, p->lut_shell, n2_lo, n2_hi, p->stream);
+            for (int c = 0; c < 12; ++c) {
+                void* comp = cplx_at(p->Q, long(c) * z.FS, z.cb);
+                p->eng->zpass(comp, z.H * d.N, +1, p->stream);
+                p->eng->ypass(comp, 1, z.FS, int(z.H), +1, 1, 0, p->stream);
+                p->eng->xpass_c2r(comp, p->real, p->stream);
+                p->eng->energy_accum(p->real, E, wcomp[c % 6], c == 0 ? 1 : 0, p->stream);
+            }
+            p->eng->subvol_sums(E, M, S_i, p->stream);
+            HIP_TRY(p, hipMemcpyAsync(p->h_sums + 1, S_i, size_t(M3) * 8, hipMemcpyDeviceToHost, p->stream));
+        }
+        HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, 8, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(p, hipMemcpyAsync(p->h_cnts, p->cnts, 8, hipMemcpyDeviceToHost, p->stream));
+        if (sigw_status s = check_launch(p)) return s;
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+        double om = 0.0;
+        int64_t nb = 0;
+        to_omega(p, 1, kt + b, p->h_sums, p->h_cnts, valid.data(), &om, &nb);
+        if (omega) omega[b] = om;
+        if (nmodes) nmodes[b] = nb;
+        double err = 0.0;
+        if (valid[0] && nb > 0) {
+            // the unnormalised inverse passes give sum_x |h|^2 = N^3 sum_n |Y|^2
+            const double inv_n3 = 1.0 / double(z.R3);
+            double S = 0.0;
+            for (long i = 0; i < M3; ++i) S += p->h_sums[1 + i] * inv_n3;
+            std::vector<double> rep(M3);
+            double mean = 0.0;
+            for (long i = 0; i < M3; ++i) {
+                const double Si = double(M3) / double(M3 - 1) * (S - p->h_sums[1 + i] * inv_n3);
+                const unsigned long long cnt = (unsigned long long)nb;
+                const int ok = 1;
+                to_omega(p, 1, kt + b, &Si, &cnt, &ok, &rep[i], nullptr);
+                mean += rep[i];
+            }
+            mean /= double(M3);
+            double var = 0.0;
+            for (long i = 0; i < M3; ++i) var += (rep[i] - mean) * (rep[i] - mean);
+            err = std::sqrt(double(M3 - 1) / double(M3) * var);
+            if (replicas) std::copy(rep.begin(), rep.end(), replicas + size_t(b) * M3);
+        } else if (replicas) {
+            std::fill(replicas + size_t(b) * M3, replicas + size_t(b + 1) * M3, 0.0);
+        }
+        if (omega_err) omega_err[b] = err;
+    }
+    return SIGW_OK;
+}
+
 sigw_status sigw_spectrum(sigw_plan_t p, int32_t slot, int32_t n_k, const double* kt, const double* lo,
                           const double* hi, double* omega, int64_t* nmodes) {
     return sigw_spectrum_batch(p, 1, &slot, n_k, kt, lo, hi, omega, nmodes);
