@@ -79,3 +79,37 @@ def test_decomposition_error_against_exact_kernels(tabs):
         p_ex += np.sum(w * spectrum.tt_power(spectrum.sym3(ex), khat))
     # the 50-term kernel changes the shell power by a modest fraction only
     assert abs(p_got / p_ex - 1.0) < 0.25, p_got / p_ex
+
+
+# ------------------------------------------------------------- per-target box
+from oracle import adaptive  # noqa: E402
+
+
+def test_kbar_against_normal_quantile():
+    """The log-normal Delta^2 is a Gaussian in log k, so k_bar = k* exp(sigma z)
+    with z the standard normal quantile of 1 - eps (scipy.stats)."""
+    from scipy import stats
+    for spec, eps in ((W.Lognormal(1e-2, 0.5, 20.0), 0.1), (W.Lognormal(5e-3, 0.3, 40.0), 0.05),
+                      (W.Lognormal(1.0, 1.2, 3.0), 0.2)):
+        kb = adaptive.k_bar(spec, eps)
+        ref = spec.k_star * math.exp(spec.sigma * stats.norm.ppf(1.0 - eps))
+        assert abs(kb - ref) <= 1e-10 * ref
+        L = adaptive.box_for_target(64, 0.5 * spec.k_star, spec, eps)
+        assert abs(L - math.pi * 64 / (3 * ref)) <= 1e-10 * L      # k below k_bar: k_bar sets the box
+        L2 = adaptive.box_for_target(64, 10 * spec.k_star, spec, eps)
+        assert abs(L2 - math.pi * 64 / (30 * spec.k_star)) <= 1e-12 * L2
+
+
+def test_adaptive_protocol_against_semi_analytic():
+    """Gaussian log-normal sigma = 0.5 at 64^3 with the per-target box: three
+    targets around the peak within 20% of Eq. semi_anal (averaged over 3 seeds)."""
+    spec = W.Lognormal(1e-2, 0.5, 10.0)
+    ks = np.array([7.0, 11.5, 16.0])
+    tabs = decomposition.tables()
+    got = np.zeros(len(ks))
+    for seed in range(3):
+        got += np.array([o for o, _, _ in adaptive.omega_adaptive(64, seed, spec, W.NGMap("gauss"), ks,
+                                                                   tabs=tabs)]) / 3
+    ref = np.array([semianalytic.omega_gauss(k, spec.A, spec.sigma, spec.k_star) for k in ks])
+    rel = np.abs(got - ref) / ref
+    assert np.all(rel < 0.2), rel
