@@ -202,6 +202,18 @@ sigw_status sigw_spectrum_jackknife(sigw_plan_t plan, int32_t slot, int32_t n_k,
                                     const double* k_lo, const double* k_hi, int32_t M, double* omega_host,
                                     int64_t* nmodes_host, double* omega_err_host, double* replicas_host);
 
+/* The paper's per-target measurement protocol (Sec. VI): for each target k
+ * the box is L_k = pi N / k_max with k_max = 3 max(k, k_bar), k_bar the
+ * wavenumber below which a fraction 1 - eps of the log-normal's power in
+ * d log k lies (eps = 0.1 in the paper); the field of this seed and map is
+ * generated in that box into the slot and Omega is measured in the thin
+ * shell k +- pi/L_k.  Writes Omega, N_b and L_k per target (any output may
+ * be NULL).  The plan's own box is restored afterwards and the slot is left
+ * empty (it held fields of other boxes).  Synchronous. */
+sigw_status sigw_spectrum_adaptive(sigw_plan_t plan, int32_t slot, uint64_t seed, const sigw_lognormal* spectrum,
+                                   const sigw_ngmap* ngmap, int32_t n_k, const double* k_targets, double eps,
+                                   double* omega_host, int64_t* nmodes_host, double* box_host);
+
 /* Asynchronous form for serving loops: enqueue the spectrum of one slot
  * (n_k <= 64) and return at once; sigw_spectrum_poll returns SIGW_E_PENDING
  * until the plan stream has finished that work, then writes the results as

@@ -33,6 +33,7 @@ EXPORTS = (
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
     "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
+    "sigw_spectrum_adaptive",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -106,6 +107,8 @@ def lib() -> ct.CDLL:
         "sigw_graph_destroy": [P],
         "sigw_autotune": [P, ct.c_int32],
         "sigw_spectrum_jackknife": [P, ct.c_int32, ct.c_int32, D, D, D, ct.c_int32, D, I64, D, D],
+        "sigw_spectrum_adaptive": [P, ct.c_int32, ct.c_uint64, ct.POINTER(Lognormal), ct.POINTER(NGMap),
+                                   ct.c_int32, D, ct.c_double, D, I64, D],
         "sigw_plan_schedule": [P, I32, I32, ct.c_char_p, ct.c_size_t],
         "sigw_plan_set_schedule": [P, ct.c_int32],
     }

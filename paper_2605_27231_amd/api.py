@@ -197,6 +197,18 @@ class Plan:
         self._chk(st, "sigw_spectrum_jackknife")
         return om, nb, err, rep
 
+    def spectrum_adaptive(self, slot: int, seed: int, spectrum, ngmap, targets, eps: float = 0.1):
+        """Per-target box protocol: (omega, nmodes, box side L) per target."""
+        t = np.ascontiguousarray(targets, dtype=np.float64)
+        n = len(t)
+        om, box = np.zeros(n), np.zeros(n)
+        nb = np.zeros(n, dtype=np.int64)
+        ls, ms = lognormal_struct(spectrum), ngmap_struct(ngmap)
+        st = lib().sigw_spectrum_adaptive(self.h, slot, ct.c_uint64(seed), ct.byref(ls), ct.byref(ms), n, _dptr(t),
+                                          float(eps), _dptr(om), _i64ptr(nb), _dptr(box))
+        self._chk(st, "sigw_spectrum_adaptive")
+        return om, nb, box
+
     def spectrum_enqueue(self, slot: int, targets, k_lo, k_hi):
         self._pend = (np.ascontiguousarray(targets, dtype=np.float64),
                       np.ascontiguousarray(k_lo, dtype=np.float64),

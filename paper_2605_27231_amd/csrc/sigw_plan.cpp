@@ -1037,6 +1037,50 @@ sigw_status sigw_spectrum_jackknife(sigw_plan_t p, int32_t slot, int32_t n_k, co
     return SIGW_OK;
 }
 
+sigw_status sigw_spectrum_adaptive(sigw_plan_t p, int32_t slot, uint64_t seed, const sigw_lognormal* sp,
+                                   const sigw_ngmap* mp, int32_t n_k, const double* kt, double eps, double* omega,
+                                   int64_t* nmodes, double* box) {
+    if (!p || !sp || !mp) return fail(p, SIGW_E_INVALID, "NULL argument");
+    if (p->pending) return fail(p, SIGW_E_STATE, "an asynchronous spectrum is still in flight");
+    if (sigw_status s = check_slot(p, slot, false)) return s;
+    if (n_k < 0 || n_k > kMaxTargets || (n_k > 0 && !kt)) return fail(p, SIGW_E_INVALID, "bad target list");
+    for (int b = 0; b < n_k; ++b)
+        if (!finite_pos(kt[b])) return fail(p, SIGW_E_INVALID, "targets must be positive and finite");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(p, SIGW_E_INVALID, "eps must be in (0, 1)");
+    if (!finite_pos(sp->sigma) || !finite_pos(sp->k_star))
+        return fail(p, SIGW_E_INVALID, "log-normal needs sigma > 0, k_star > 0");
+    // k_bar: Delta^2 is a normal density in log k (mean log k*, width sigma),
+    // so the power fraction below k is Phi((log k - log k*)/sigma); invert
+    // Phi(z) = 1 - eps by bisection
+    double za = -40.0, zb = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        const double zm = 0.5 * (za + zb);
+        if (0.5 * std::erfc(-zm / std::sqrt(2.0)) < 1.0 - eps) za = zm;
+        else zb = zm;
+    }
+    const double kbar = sp->k_star * std::exp(sp->sigma * 0.5 * (za + zb));
+    const double L0 = p->d.L;
+    sigw_status st = SIGW_OK;
+    for (int b = 0; b < n_k && st == SIGW_OK; ++b) {
+        const double L = kPi * p->d.N / (3.0 * std::max(kt[b], kbar));
+        p->d.L = L;
+        st = sigw_generate_field(p, slot, seed, sp, mp);
+        double om = 0.0;
+        int64_t nb = 0;
+        if (st == SIGW_OK) {
+            const double lo = kt[b] - kPi / L, hi = kt[b] + kPi / L;
+            st = sigw_spectrum(p, slot, 1, kt + b, &lo, &hi, &om, &nb);
+        }
+        if (omega) omega[b] = om;
+        if (nmodes) nmodes[b] = nb;
+        if (box) box[b] = L;
+    }
+    // the slot now holds a field of the last target's box: it must be generated again
+    p->d.L = L0;
+    p->has_field[slot] = 0;
+    return st;
+}
+
 sigw_status sigw_spectrum(sigw_plan_t p, int32_t slot, int32_t n_k, const double* kt, const double* lo,
                           const double* hi, double* omega, int64_t* nmodes) {
     return sigw_spectrum_batch(p, 1, &slot, n_k, kt, lo, hi, omega, nmodes);
