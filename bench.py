@@ -39,11 +39,13 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-# (scaled by a 1 GiB copy: reads x2.0, writes x1.0), valid only for the
-# kernel source they were taken on; see profiles/hbm_counters_localNG256_fp32.md.
-COUNTER_SOURCE_SHA = "462ff91324736580"
-COUNTER_TRAFFIC = {"xprod": 10274046397.5, "ypass": 16908177587.9, "gen_z": 6841149522.0}
+# HBM bytes per launch (four realisations per launch, the benchmark's
+# configuration) from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
+# `bench.py --quick`, scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid
+# only for the kernel source they were taken on (see the summaries in
+# profiles/).
+COUNTER_SOURCE_SHA = "13fd3e91a72a9661"
+COUNTER_TRAFFIC = {"xprod": 41322519454.7, "ypass": 67632360196.1, "gen_z": 27396699362.4}
 
 
 def kernel_source_sha() -> str:
@@ -102,8 +104,12 @@ def run_gpu(args):
     job = WORKLOADS[args.workload]["job"]()
     seeds = list(job.seeds)
     prec = "f32"
-    # the autotuner picks the x-pass schedule at creation (outside the timed region)
-    plan = P.Plan(job.N, L=job.L, prec=prec, n_slots=len(seeds), autotune=1)
+    # all realisations of a step go through each kernel launch together
+    # (grid y) when their workspaces fit comfortably (N <= 256: 4 x 18 GB);
+    # the autotuner picks the x-pass schedule at creation (outside the timed
+    # region)
+    batch = len(seeds) if job.N <= 256 else 1
+    plan = P.Plan(job.N, L=job.L, prec=prec, n_slots=len(seeds), batch=batch, autotune=1)
     schedule = plan.schedule()[2]
     cb = 8
     per_seed = {}
@@ -112,15 +118,19 @@ def run_gpu(args):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     def step(lat):
-        for i, s in enumerate(seeds):
+        for g0 in range(0, len(seeds), batch):
+            grp = list(range(g0, min(g0 + batch, len(seeds))))
             t0 = time.perf_counter()
-            plan.generate_field(i, s, job.spectrum, job.ngmap)
-            om, nb = plan.spectrum(i, job.targets, job.k_lo, job.k_hi)
-            lat.append(time.perf_counter() - t0)
-            per_seed[s] = om
+            for i in grp:
+                plan.generate_field(i, seeds[i], job.spectrum, job.ngmap)
+            om_b, nb_b = plan.spectrum_batch(grp, job.targets, job.k_lo, job.k_hi)
+            dt = time.perf_counter() - t0
+            for j, i in enumerate(grp):
+                lat.append(dt)
+                per_seed[seeds[i]] = om_b[j]
             if job.N > 256:
-                say(f"seed {s}: {lat[-1]:.2f} s")
-        return om, nb
+                say(f"seeds {[seeds[i] for i in grp]}: {dt:.2f} s")
+        return om_b[-1], nb_b[-1]
 
     for i in range(args.warmup):
         tw = time.perf_counter()
@@ -142,7 +152,7 @@ def run_gpu(args):
 
     times = {k: plan.kernel_time(k) for k in ("gen_z", "ypass", "xprod", "ypass_q", "zbin")}
     plan.set_timing(False)
-    ab = algorithmic_bytes(job.N, cb, 50, job.N // 2 + 1)
+    ab = {k: v * batch for k, v in algorithmic_bytes(job.N, cb, 50, job.N // 2 + 1).items()}
     # dominant kernel: the one with the largest total time in the timed region
     dom = max(("gen_z", "ypass", "xprod"), key=lambda k: times[k][0] * times[k][1])
     ms_d, n_d = times[dom]
@@ -169,7 +179,9 @@ def run_gpu(args):
         "kernels": kernels,
         "schedule": schedule,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "what": f"one spectrum (field generation + {len(job.targets)} bins) end to end"},
+                       "what": f"one spectrum (field generation + {len(job.targets)} bins) end to end; "
+                               f"the {batch} spectra of a batch complete together"},
+        "batch": batch,
         "omega_seed_mean": np.mean([per_seed[s] for s in seeds], axis=0).tolist(),
         "targets": job.targets.tolist(),
         "nmodes": nb.tolist(),
@@ -201,17 +213,23 @@ def run_gpu(args):
 
 
 def quick_profile():
-    """A short run for hardware-counter passes: one 256^3 field, the peak
-    target, and a plain 1 GiB device copy whose counter readings calibrate
-    the byte counters (read 1 GiB, write 1 GiB)."""
+    """A short run for hardware-counter passes, in the benchmark's launch
+    configuration: the four 256^3 fields in one batch, the peak target (one
+    launch of each hot kernel per kernel m), and a plain 1 GiB device copy
+    whose counter readings calibrate the byte counters (read 1 GiB, write
+    1 GiB)."""
     import torch
     import paper_2605_27231_amd as P
 
     job = W.config_local_ng(256, 64)
     b = int(np.argmin(np.abs(job.targets - job.spectrum.k_star * 2 / math.sqrt(3))))
-    with P.Plan(job.N, L=job.L, prec="f32") as plan:
-        plan.generate_field(0, 0, job.spectrum, job.ngmap)
-        om, nb = plan.spectrum(0, job.targets[b:b + 1], job.k_lo[b:b + 1], job.k_hi[b:b + 1])
+    n = len(job.seeds)
+    with P.Plan(job.N, L=job.L, prec="f32", n_slots=n, batch=n) as plan:
+        for i, s in enumerate(job.seeds):
+            plan.generate_field(i, s, job.spectrum, job.ngmap)
+        om, nb = plan.spectrum_batch(list(range(n)), job.targets[b:b + 1], job.k_lo[b:b + 1],
+                                     job.k_hi[b:b + 1])
+        om, nb = om[0], nb[0]
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)
