@@ -49,10 +49,13 @@ COUNTER_TRAFFIC = {"xprod": 41322519454.7, "ypass": 67632360196.1, "gen_z": 2739
 
 
 def kernel_source_sha() -> str:
+    """Hash of the device code (kernels and the FFT header they include)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2605_27231_amd", "csrc", "sigw_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("sigw_kernels.hip", "sigw_fft.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_27231_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stage_terms(N: int, cb: int, n_alpha: int = 50) -> int:

@@ -197,10 +197,9 @@ template <> struct TwoPhase<512> { static constexpr int R1 = 16; };
 // ld(line, n) supplies x; st(line, k, X) consumes the output.  LINE_FAST puts
 // consecutive threads on consecutive lines (for tiles whose lines are
 // interleaved in memory); otherwise consecutive threads walk along a line.
-// lds must hold NL * N complex (plus NL * R1 for the !LINE_FAST padding).
-// The routine starts and ends without a barrier of its own on the LDS
-// buffer other than the one between the phases; the caller synchronises
-// before lds is reused.
+// lds must hold TPLayout<N, NL, LINE_FAST>::size complex values (NL * N
+// plus padding).  The phases contain no barrier: the caller synchronises
+// between phase 1 and phase 2 and before the buffer is reused.
 // ----------------------------------------------------------------------------
 template <int N, int NL, bool LINE_FAST> struct TPLayout {
     static constexpr int R1 = TwoPhase<N>::R1;

@@ -30,12 +30,6 @@ template <typename R, int N> struct Shape {
     static constexpr long FS = long(H) * N * N;           // complex elements per half spectrum
     // y-pass / x-pass chunk of contiguous z values (128-byte runs of complex)
     static constexpr int TZ = (sizeof(R) == 4 ? 16 : 8) < N ? (sizeof(R) == 4 ? 16 : 8) : N;
-    // z-pass rows per block
-    static constexpr int RBZ = (N >= 1024) ? 1 : (N >= 512 ? 4 : (N >= 256 ? 8 : (2048 / N)));
-    static constexpr int RBZ_ = (N == 384) ? 4 : RBZ;
-    // gen_z rows per block (a divisor of N, so blocks tile the (N/2+1) N rows)
-    static constexpr int RBG = (N >= 512) ? 1 : (512 / N < N ? 512 / N : N);
-    static constexpr int RBG_ = (N == 384) ? 1 : RBG;
     // zbin rows per block (a divisor of N)
     static constexpr int RBB = (N >= 256) ? 1 : (256 / N < N ? 256 / N : N);
     static constexpr int RBB_ = (N == 384) ? 1 : RBB;
