@@ -47,6 +47,23 @@ def sampled(job, seeds_bins, name, note):
         json.dump(out, f, indent=1)
 
 
+def ensemble_sampled(jobs, bins, name, note):
+    """Sampled bins of several realisations, each with its own parameters."""
+    tabs = decomposition.tables()
+    out = {"name": name, "note": note, "jobs": [_job_dict(j) | {"seed": int(j.seeds[0])} for j in jobs],
+           "samples": [], "generated_by": "python tests/golden/make_golden.py " + name}
+    for r, job in enumerate(jobs):
+        t0 = time.time()
+        ph = field.phi_hat(job.N, job.L, job.seeds[0], job.spectrum, job.ngmap)
+        for b in bins:
+            om, nb = spectrum.omega_target(ph, tabs[0], tabs[1], job.targets[b], job.k_lo[b], job.k_hi[b], job.L)
+            out["samples"].append({"realisation": r, "bin": int(b), "target": float(job.targets[b]),
+                                   "omega": float(om), "nmodes": int(nb)})
+            print(name, r, b, om, nb, f"{time.time() - t0:.0f}s", flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 FIXTURES = {
     # 256^3 local NG (f_NL = 5), 64 log bins, seeds 0..3: low tail, rise, peak, high tail
     "local256_fp64_oracle": lambda: sampled(
@@ -56,6 +73,11 @@ FIXTURES = {
     "exptail512_fp64_oracle": lambda: sampled(
         W.config_exptail(512, 96), [(0, [44, 66, 80])], "exptail512_fp64_oracle",
         "512^3 exp-tail beta=3 clip 1e-6, A=5e-3, sigma=0.3, k*=40, 96 log bins; FP64 oracle"),
+    # the first four realisations of the 128^3 ensemble (parameters drawn per realisation), 32 log bins
+    "ensemble128_fp64_oracle": lambda: ensemble_sampled(
+        W.config_ensemble(128, 4, 32), [10, 18, 24], "ensemble128_fp64_oracle",
+        "128^3 local NG, per-realisation f_NL, sigma, k* (PCG64 seed 2605), 32 log bins, "
+        "realisations 0..3; FP64 oracle"),
 }
 
 if __name__ == "__main__":

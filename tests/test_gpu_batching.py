@@ -3,7 +3,8 @@
 * An ensemble of realisations with different seeds and parameter points,
   several per launch and replayed from a captured HIP graph, gives each
   realisation the same bits as computing it alone, and matches the FP64
-  oracle within 1e-4 per bin (FP32 path).
+  oracle within 1e-4 per bin (FP32 path); at 32^3 against the oracle run
+  in the test, at 128^3 (the ensemble recipe) against stored oracle values.
 * Graph replays, with eager work of the same plan between them, each equal
   the eager result for the fields the slots hold at that time.
 * Served requests of mixed lattice sizes that overlap on the device give
@@ -63,6 +64,36 @@ def test_ensemble_batched_graph_equals_alone_and_oracle():
         ok = nref > 0
         np.testing.assert_array_equal(res.nmodes[r], nref)
         assert np.max(np.abs(res.omega[r][ok] - ref[ok]) / np.abs(ref[ok])) <= 1e-4
+
+
+def test_ensemble128_batched_graph_matches_oracle():
+    """The 128^3 ensemble recipe (per-realisation f_NL, sigma, k*): its first
+    four realisations in one batch of 4, replayed from a graph, equal each
+    realisation alone bit for bit and the FP64 oracle values of sampled bins
+    (tests/golden/ensemble128_fp64_oracle.json) within 1e-4."""
+    import json
+    import os
+    from paper_2605_27231_amd.ensemble import Ensemble
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "ensemble128_fp64_oracle.json")) as f:
+        g = json.load(f)
+    jobs = W.config_ensemble(128, 4, 32)
+    for job, gj in zip(jobs, g["jobs"]):
+        assert (gj["N"], gj["sigma"], gj["k_star"], gj["F_NL"], gj["seed"]) == \
+            (job.N, job.spectrum.sigma, job.spectrum.k_star, job.ngmap.F_NL, job.seeds[0])
+    print("ensemble 4 x 128^3, batch 4, graph", flush=True)
+    with Ensemble(jobs, batch=4, graph=True) as ens:
+        res = ens.run()
+    for r, job in enumerate(jobs):
+        om, nb = _alone(job)
+        np.testing.assert_array_equal(res.omega[r], om)
+        np.testing.assert_array_equal(res.nmodes[r], nb)
+    for smp in g["samples"]:
+        r, b = smp["realisation"], smp["bin"]
+        assert res.nmodes[r][b] == smp["nmodes"]
+        rel = abs(res.omega[r][b] - smp["omega"]) / abs(smp["omega"])
+        print(f"  realisation {r} bin {b} rel err {rel:.1e}", flush=True)
+        assert rel <= 1e-4
 
 
 def test_graph_replays_match_eager():
