@@ -101,3 +101,28 @@ def test_library_kernel_table_other_meta_parameters():
     K_lib = (phi * s) @ phi.T
     K_or = (tab.phi * tab.sigma) @ tab.phi.T
     assert np.max(np.abs(K_lib - K_or)) <= 1e-12 * np.max(np.abs(K_or))
+
+
+def test_footprint_batch_and_tables_cache():
+    """Each batch member brings its own workspace (gradient fields, staging,
+    Q); the Sec. V tables come back identical from the process-wide cache."""
+    base = P.sigw_plan_footprint(P.plan_desc(128))
+    four = P.sigw_plan_footprint(P.plan_desc(128, batch=4))
+    fs, cb = 65 * 128 * 128, 8
+    stage = max(1, min(50, (16 << 30) // (2 * fs * cb)))
+    per_member = (3 * 50 + 2 * stage + 12) * fs * cb
+    assert four - base == 3 * per_member + 3 * 65 * 128 * 16
+    assert P.sigw_plan_footprint(P.plan_desc(128, autotune=1)) == base
+    a = P.sigw_kernel_table(P.plan_desc(64), 1)
+    b = P.sigw_kernel_table(P.plan_desc(256), 1)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_new_entry_points_reject_null_plans():
+    L = _lib.lib()
+    D = ct.POINTER(ct.c_double)
+    assert L.sigw_spectrum_jackknife(None, 0, 0, None, None, None, 4, None, None, None, None) == \
+        _lib.SIGW_E_INVALID
+    assert L.sigw_spectrum_adaptive(None, 0, 0, None, None, 0, None, 0.1, None, None, None) == \
+        _lib.SIGW_E_INVALID
