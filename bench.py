@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --quick`, scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid
 # only for the kernel source they were taken on (see the summaries in
 # profiles/).
-COUNTER_SOURCE_SHA = "996c044415c59409"
-COUNTER_TRAFFIC = {"xprod": 41226774679.4, "ypass": 67632270306.2, "gen_z": 27393521595.1}
+COUNTER_SOURCE_SHA = "a9a4f6bf5777aae4"
+COUNTER_TRAFFIC = {"xprod": 41235657669.3, "ypass": 67632056252.6, "gen_z": 27392876405.1}
 
 
 def kernel_source_sha() -> str:

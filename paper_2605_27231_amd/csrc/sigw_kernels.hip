@@ -648,16 +648,22 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     // with more, registers are too scarce and U_y reads it again
     constexpr bool KEEP = PER == 1;
     C wr[1][R1];
+    C zr[R1];
     if constexpr (KEEP) {
+        // Z first, then W: the U_z round runs first and waits only for Z,
+        // while the W loads stay in flight behind it
         const int it = tid;
         const bool ok = (ITEMS % NT == 0) || it < ITEMS;
         const int line = it % TZ, t = it / TZ;
 #pragma unroll
+        for (int m = 0; m < R1; ++m) zr[m] = ok ? z[long(t + R2 * m) * N + line] : cmk<C>(R(0), R(0));
+#pragma unroll
         for (int m = 0; m < R1; ++m) wr[0][m] = ok ? w[long(t + R2 * m) * N + line] : cmk<C>(R(0), R(0));
     }
     __syncthreads();                                        // twl
-#pragma unroll 1
-    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+        const int j = KEEP ? (jj + 2) % 3 : jj;             // rounds U_z, U_x, U_y when W is kept
         if constexpr (KEEP) {
             const int it = tid;
             if ((ITEMS % NT == 0) || it < ITEMS) {
@@ -667,7 +673,7 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
                 for (int m = 0; m < R1; ++m) {
                     const int yy = t + R2 * m;
                     if (j == 2) {
-                        v[m] = z[long(yy) * N + line];
+                        v[m] = zr[m];
                     } else {
                         R q = qx;
                         if (j == 1) {
