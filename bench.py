@@ -40,12 +40,12 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch (four realisations per launch, the benchmark's
-# configuration) from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
-# `bench.py --quick`, scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid
-# only for the kernel source they were taken on (see the summaries in
-# profiles/).
-COUNTER_SOURCE_SHA = "a9a4f6bf5777aae4"
-COUNTER_TRAFFIC = {"xprod": 41235657669.3, "ypass": 67632056252.6, "gen_z": 27392876405.1}
+# configuration and launch mix), averaged over the launches of one spectrum,
+# from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on `bench.py --quick`,
+# scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
+# source they were taken on (see the summaries in profiles/).
+COUNTER_SOURCE_SHA = "2b11115b1ab3bde5"
+COUNTER_TRAFFIC = {"xprod": 33078903830.1, "ypass": 51249631772.7, "gen_z": 19059039185.7}
 
 
 def kernel_source_sha() -> str:
@@ -65,23 +65,71 @@ def stage_terms(N: int, cb: int, n_alpha: int = 50) -> int:
     return max(1, min(n_alpha, (16 << 30) // (2 * FS * cb)))
 
 
-def algorithmic_bytes(N: int, cb: int, n_alpha: int, n_planes: int):
+def shell_n2_hi(N: int, L: float, k_lo: float, k_hi: float):
+    """Largest integer |n|^2 of the shell k_lo <= k_F |n| < k_hi (None when
+    the shell holds no lattice mode); the planes kx <= sqrt of it carry the
+    shell."""
+    kF = 2 * math.pi / L
+    n2 = np.arange(3 * (N // 2) ** 2 + 1)
+    k = kF * np.sqrt(n2)
+    sel = n2[(n2 > 0) & (k >= k_lo) & (k < k_hi)]
+    return int(sel[-1]) if len(sel) else None
+
+
+def support_n2(N: int, L: float, k: float, u_max: float) -> int:
+    """Bound on |n|^2 of the modes where phi_a(k_F |n| / k) can be non-zero
+    (u below the last grid edge u_max); the same bound the library prunes
+    with."""
+    kF = 2 * math.pi / L
+    r = u_max * k / kF
+    r2 = r * r * (1.0 + 1e-12) + 1.0
+    n2max = 3 * (N // 2) ** 2
+    return n2max if r2 >= n2max else int(r2)
+
+
+def algorithmic_bytes(N: int, L: float, cb: int, n_alpha: int, u_max: float, targets, k_lo, k_hi):
     """Compulsory HBM bytes per launch of each hot kernel (each input read
-    once, each output written once), for one target and one kernel m.
-    FS = (N/2+1) N^2 complex elements make one half spectrum; st = terms
-    staged per gen_z / ypass3 launch."""
+    once, each output written once), averaged over the launches of one
+    spectrum: one launch per target with modes and kernel m (gen_z and
+    ypass3: one per staged group of st terms).  Only the support of the
+    weighted fields counts: rows (kx, ky) with nx^2 + ny^2 <= n2_sup after
+    the z pass, planes kx <= kx_sup after the y pass; everything outside is
+    zero and is neither read nor written."""
     H = N // 2 + 1
-    FS = H * N * N
     plane = N * N
     st = stage_terms(N, cb, n_alpha)
-    return {
-        # reads Phi_hat, writes the (W, Z) pair of each staged term
-        "gen_z": (FS + 2 * st * FS) * cb,
-        # reads the staged pairs, writes 3 gradient fields per term
-        "ypass": (2 * st * FS + 3 * st * FS) * cb,
-        # reads all 3 n_alpha gradient fields, writes 6 components on the planes the shell needs
-        "xprod": (3 * n_alpha * FS + 6 * n_planes * plane) * cb,
-    }
+    groups = [min(st, n_alpha - a) for a in range(0, n_alpha, st)]
+    ny2 = np.fft.fftfreq(N, 1.0 / N) ** 2
+    tot = {"gen_z": 0.0, "ypass": 0.0, "xprod": 0.0}
+    cnt = {"gen_z": 0, "ypass": 0, "xprod": 0}
+    for kt, lo, hi in zip(targets, k_lo, k_hi):
+        n2_hi = shell_n2_hi(N, L, lo, hi)
+        if n2_hi is None:
+            continue                                   # empty shell: no launches
+        n2s = support_n2(N, L, kt, u_max)
+        kxs = min(H - 1, math.isqrt(n2s))
+        n_planes = min(H - 1, math.isqrt(n2_hi)) + 1
+        kx2 = np.arange(kxs + 1)[:, None] ** 2
+        rows = int(((kx2 + ny2[None, :]) <= n2s).sum())   # live (kx, ky) rows
+        for g in groups:
+            # reads Phi_hat on the live rows, writes the (W, Z) pair of each term there
+            tot["gen_z"] += (rows * N + 2 * g * rows * N) * cb
+            # reads the live rows of the pairs, writes 3 gradient fields per term on kx <= kx_sup
+            tot["ypass"] += (2 * g * rows * N + 3 * g * (kxs + 1) * plane) * cb
+            cnt["gen_z"] += 1
+            cnt["ypass"] += 1
+        # reads the 3 n_alpha gradient fields on kx <= kx_sup, writes 6 components on the shell's planes
+        tot["xprod"] += (3 * n_alpha * (kxs + 1) * plane + 6 * n_planes * plane) * cb
+        cnt["xprod"] += 1
+    return {k: (tot[k] / cnt[k] if cnt[k] else 0.0) for k in tot}
+
+
+def kernel_u_max(N: int, prec: str = "f32") -> float:
+    """Last edge of the kernel table's u grid (the support of every phi_a)."""
+    import paper_2605_27231_amd as P
+    from paper_2605_27231_amd import api
+    _, _, edges = api.sigw_kernel_table(P.plan_desc(N, prec=prec), 0)
+    return float(edges[-1])
 
 
 WORKLOADS = {
@@ -155,7 +203,9 @@ def run_gpu(args):
 
     times = {k: plan.kernel_time(k) for k in ("gen_z", "ypass", "xprod", "ypass_q", "zbin")}
     plan.set_timing(False)
-    ab = {k: v * batch for k, v in algorithmic_bytes(job.N, cb, 50, job.N // 2 + 1).items()}
+    u_max = kernel_u_max(job.N, prec)
+    ab = {k: int(round(v * batch))
+          for k, v in algorithmic_bytes(job.N, job.L, cb, 50, u_max, job.targets, job.k_lo, job.k_hi).items()}
     # dominant kernel: the one with the largest total time in the timed region
     dom = max(("gen_z", "ypass", "xprod"), key=lambda k: times[k][0] * times[k][1])
     ms_d, n_d = times[dom]
@@ -217,22 +267,22 @@ def run_gpu(args):
 
 def quick_profile():
     """A short run for hardware-counter passes, in the benchmark's launch
-    configuration: the four 256^3 fields in one batch, the peak target (one
-    launch of each hot kernel per kernel m), and a plain 1 GiB device copy
-    whose counter readings calibrate the byte counters (read 1 GiB, write
-    1 GiB)."""
+    configuration and launch mix: the four 256^3 fields in one batch through
+    every target of the spectrum (one step, so the per-launch averages of the
+    counters cover the same launches as the benchmark's), and a plain 1 GiB
+    device copy whose counter readings calibrate the byte counters (read
+    1 GiB, write 1 GiB)."""
     import torch
     import paper_2605_27231_amd as P
 
     job = W.config_local_ng(256, 64)
     b = int(np.argmin(np.abs(job.targets - job.spectrum.k_star * 2 / math.sqrt(3))))
     n = len(job.seeds)
-    with P.Plan(job.N, L=job.L, prec="f32", n_slots=n, batch=n) as plan:
+    with P.Plan(job.N, L=job.L, prec="f32", n_slots=n, batch=n, autotune=1) as plan:
         for i, s in enumerate(job.seeds):
             plan.generate_field(i, s, job.spectrum, job.ngmap)
-        om, nb = plan.spectrum_batch(list(range(n)), job.targets[b:b + 1], job.k_lo[b:b + 1],
-                                     job.k_hi[b:b + 1])
-        om, nb = om[0], nb[0]
+        om, nb = plan.spectrum_batch(list(range(n)), job.targets, job.k_lo, job.k_hi)
+        om, nb = om[0][b:b + 1], nb[0][b:b + 1]
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)

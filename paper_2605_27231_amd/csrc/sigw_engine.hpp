@@ -59,23 +59,31 @@ struct Engine {
     // (grid y); member b works on the realisation in slot sel[b] and on its
     // own workspace, found at b times the given stride.
     //
+    // Support bound n2_sup: every mode with phi_a(u(n)) != 0 has |n|^2 <=
+    // n2_sup.  A (kx, ky) row with nx^2 + ny^2 > n2_sup is zero after the z
+    // pass and a kx plane with kx^2 > n2_sup is zero after the y pass; gen_z
+    // does not write such rows, ypass3 reads them as zeros and writes only
+    // the planes kx <= kx_sup = min(N/2, floor(sqrt(n2_sup))), and xprod
+    // reads only those planes.  All three must get the same bound.
+    //
     // Fused weighting + inverse DFT along z: for a = a0..a0+na-1,
     // S[2(a-a0)] = IDFT_z( phi_a(u) Phi_hat / V ), S[2(a-a0)+1] = IDFT_z( i qt_z phi_a(u) Phi_hat / V ).
     virtual void gen_z(const void* phi_hat_slots, const int* sel, int nb, const int16_t* lut_u,
                        const void* phi_tab, int n_alpha, int a0, int na, double k_F, double inv_V,
-                       void* S, long s_stride, hipStream_t s) = 0;
+                       void* S, long s_stride, int n2_sup, hipStream_t s) = 0;
     // Inverse DFT along y of na terms' (W, Z) pairs into their three gradient
     // fields T[3a + j]: i qt_x IDFT_y(W), IDFT_y(i qt_y W), IDFT_y(Z), stored
     // in the x-pass tile layout.
     virtual void ypass3(const void* S, int na, int nb, long s_stride, void* T, long t_stride, double k_F,
-                        hipStream_t s) = 0;
+                        int n2_sup, hipStream_t s) = 0;
     // Fused inverse DFT along x + products + forward DFT along x:
     // Qx_c = DFT_x( sum_a sigma_a dV G_a,i G_a,j ) for the 6 components, on
     // the kx planes [0, n_planes); accumulate adds into Qx instead of storing.
+    // The planes kx > kx_sup of T are taken as zero and not read.
     // Runs the active x-pass schedule.
     virtual void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na,
                        double dV, double k_F, void* Qx, long q_stride, int n_planes, int accumulate,
-                       hipStream_t s) = 0;
+                       int kx_sup, hipStream_t s) = 0;
     // x-pass schedules compiled for this size (index 0 is the default): z
     // chunk width and blocks-per-CU target of schedule i; the active one.
     // Every schedule computes the same values in the same order.

@@ -254,6 +254,27 @@ __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* tw, int tid)
     }
 }
 
+// As tp_phase1, with ld(line, t, m) returning element t + R2 m of a line;
+// m is a constant once the loop is unrolled, so ld can branch on it freely.
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
+__device__ __forceinline__ void tp_phase1_tm(LD&& ld, C* lds, const C* tw, int tid) {
+    using Lay = TPLayout<N, NL, LINE_FAST>;
+    constexpr int R1 = Lay::R1, R2 = Lay::R2;
+    constexpr int ITEMS = NL * R2;
+#pragma unroll
+    for (int w0 = 0; w0 < ITEMS; w0 += NT) {
+        const int w = w0 + tid;
+        if ((ITEMS % NT == 0) || w < ITEMS) {
+            const int line = LINE_FAST ? w % NL : w / R2;
+            const int t = LINE_FAST ? w / NL : w % R2;
+            C a[R1];
+#pragma unroll
+            for (int m = 0; m < R1; ++m) a[m] = ld(line, t, m);
+            tp_phase1_item<C, N, SIGN, NL, LINE_FAST>(a, line, t, lds, tw);
+        }
+    }
+}
+
 // Copy of the N-entry twiddle table into LDS, for the lane-dependent twiddles
 // of phase 1 (the caller synchronises before use).
 template <typename C, int N, int NT>

@@ -14,6 +14,7 @@
 // last forward pass (zbin).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -66,6 +67,27 @@ template <typename R, int N> struct TTile {
 template <int N, int TZT>
 __device__ __forceinline__ long t_offset(int kx, int y, int z) {
     return ((long(y) * (N / TZT) + z / TZT) * (N / 2 + 1) + kx) * TZT + z % TZT;
+}
+
+// Raw buffer loads of complex values.  The descriptor covers `bytes` bytes
+// from a wave-uniform base; a load whose byte offset is at or past that
+// count returns zero and makes no memory access (the buffer unit's range
+// check), which is how known-zero elements are read without predication.
+constexpr unsigned kBufOutside = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+    // third word 0x00020000: 32-bit data format, as the gfx9 family expects
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), 0x00020000);
+}
+typedef unsigned BufU2 __attribute__((ext_vector_type(2)));
+typedef unsigned BufU4 __attribute__((ext_vector_type(4)));
+template <typename C> __device__ __forceinline__ C buf_load(__amdgpu_buffer_rsrc_t rs, unsigned off);
+template <> __device__ __forceinline__ float2 buf_load<float2>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+    const BufU2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+template <> __device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+    const BufU4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    return make_double2(__hiloint2double(int(v.y), int(v.x)), __hiloint2double(int(v.w), int(v.z)));
 }
 
 // ----------------------------------------------------------------------------
@@ -506,6 +528,9 @@ __global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_tar
 //   W_a = IDFT_z( phi_a(u) Phi_hat / V ),  Z_a = IDFT_z( i qt_z phi_a(u) Phi_hat / V ).
 // The x and y gradients are applied later (i qt_y before the y transform,
 // i qt_x in the x pass), so two fields per term cross HBM here, not three.
+// Rows outside the support (nx^2 + ny^2 > n2_sup) are zero for every term:
+// they are neither read nor written (ypass3 reads them as zeros), and the
+// grid covers only the planes kx <= kx_sup.
 // ----------------------------------------------------------------------------
 template <typename R, int N> struct GCfg {
     static constexpr int R1 = TPConst<N>::R1;
@@ -520,7 +545,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
                                                const int* __restrict__ sel, const int16_t* __restrict__ lut_u,
                                                const R* __restrict__ phi_tab, int n_alpha, int a0, int na, R k_F,
                                                R inv_V, typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
-                                               const typename CplxOf<R>::T* __restrict__ tw) {
+                                               int n2_sup, const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using G = GCfg<R, N>;
     constexpr int RB = G::RB, NT = G::NT, R1 = G::R1, R2 = G::R2;
@@ -530,8 +555,21 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
     constexpr int ITEMS = RB * R2;
     constexpr int PER = (ITEMS + NT - 1) / NT;
     __shared__ C lds[Lay::size];
+    static_assert(N % RB == 0 && RB <= 32, "the rows of a block share one kx plane");
     const int tid = threadIdx.x;
     const long row0 = long(blockIdx.x) * RB;
+    // rows of this block inside the support: bit row of live
+    unsigned live = 0;
+    {
+        const int nx = signed_index(int(row0 / N), N);
+        const int lim = n2_sup - nx * nx;
+#pragma unroll
+        for (int row = 0; row < RB; ++row) {
+            const int ny = signed_index(int((row0 + row) % N), N);
+            if (ny * ny <= lim) live |= 1u << row;
+        }
+    }
+    if (live == 0) return;                                  // uniform over the block
     // batch member blockIdx.y works on the realisation in slot sel[blockIdx.y]
     const C* phi_hat = phi_hat_all + long(sel[blockIdx.y]) * FS;
     C* T = S_all + blockIdx.y * s_stride;
@@ -540,8 +578,10 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int w = tid + i * NT;
-        const bool ok = (ITEMS % NT == 0) || w < ITEMS;
-        const int row = ok ? w / R2 : 0, t = ok ? w % R2 : 0;
+        const bool inr = (ITEMS % NT == 0) || w < ITEMS;
+        const int row = inr ? w / R2 : 0;
+        const bool ok = inr && ((live >> row) & 1u);
+        const int t = ok ? w % R2 : 0;
         const long r = row0 + row;
         const int kx = int(r / N), ky = int(r % N);
         const int nx = signed_index(kx, N), ny = signed_index(ky, N);
@@ -593,7 +633,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
         const long fbase = long(2 * (a - a0)) * FS;
         auto st = [&](int line, int kz, C v) {
             const int j = line / RB, row = line % RB;
-            T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
+            if ((live >> row) & 1u) T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
         };
         tp_phase2<C, N, +1, NL, NT, false>(st, lds, tid);
         __syncthreads();
@@ -608,10 +648,14 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
 // here and leaves the x pass a uniform Hermitian extension).  Tile (term,
 // kx plane, z chunk); the three outputs are transformed one after another
 // through the same LDS tile and stored in the x-pass tile layout (t_offset).
+// The grid covers the planes kx < hs = kx_sup + 1 only; rows of the input
+// outside the support (nx^2 + ny^2 > n2_sup) were not written by gen_z and
+// are read as zeros.
 // ----------------------------------------------------------------------------
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
                                                 typename CplxOf<R>::T* __restrict__ T_all, long t_stride, R k_F,
+                                                int n2_sup, int hs,
                                                 const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     constexpr int TZ = YCfg<R, N>::TZ;
@@ -635,13 +679,41 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     const long b = xcd_block(int(blockIdx.x), int(gridDim.x));
     const int zc = int(b % NZC);
     const long fp = b / NZC;
-    const int kx = int(fp % H);
-    const long al = fp / H;
+    const int kx = int(fp % hs);
+    const long al = fp / hs;
     const long off = long(kx) * N * N + zc * TZ;
     const C* S = S_all + blockIdx.y * s_stride;
     C* T = T_all + blockIdx.y * t_stride;
     const C* w = S + 2 * al * FS + off;
     const C* z = w + FS;
+    // Rows of the input outside the support read as zeros.  The live rows
+    // are ny in [-ylim, ylim] (lim >= 0 on the planes kx <= kx_sup): the
+    // prefix y <= ylim and the suffix y >= N - ylim.  Descriptor lo covers
+    // the prefix from the plane's start, descriptor hi the suffix from its
+    // first row; the buffer range check returns zeros for every dead row (an
+    // offset below the suffix wraps to a large unsigned value, and so does
+    // kBufOutside for items past the tile), so the loads carry no
+    // per-element predicate.
+    const int lim = n2_sup - kx * kx;
+    int ylim = int(sqrtf(float(lim)));
+    while (ylim > 0 && ylim * ylim > lim) --ylim;
+    while ((ylim + 1) * (ylim + 1) <= lim) ++ylim;
+    ylim = ylim < N / 2 ? ylim : N / 2;
+    static_assert(long(N) * N * sizeof(C) < kBufOutside / 2, "plane offsets fit the buffer range");
+    constexpr int RowB = N * int(sizeof(C));
+    const auto zlo = buf_rsrc(z, unsigned((ylim + 1) * RowB));
+    const auto wlo = buf_rsrc(w, unsigned((ylim + 1) * RowB));
+    const auto zhi = buf_rsrc(z + long(N - ylim) * N, unsigned(ylim * RowB));
+    const auto whi = buf_rsrc(w + long(N - ylim) * N, unsigned(ylim * RowB));
+    // element (row t + R2 m, z line) of this lane; lane_off = (t N + line) * sizeof(C)
+    auto load_row = [&](const __amdgpu_buffer_rsrc_t& lo, const __amdgpu_buffer_rsrc_t& hi, unsigned lane_off,
+                        int t, int m) -> C {
+        const unsigned o = lane_off + unsigned(R2 * m * RowB);
+        const unsigned oh = o - unsigned((N - ylim) * RowB);
+        if (R2 * (m + 1) <= N / 2) return buf_load<C>(lo, o);     // lower half for every t
+        if (R2 * m >= N / 2) return buf_load<C>(hi, oh);          // upper half for every t
+        return (t + R2 * m < N / 2) ? buf_load<C>(lo, o) : buf_load<C>(hi, oh);
+    };
     const R qx = (kx == N / 2) ? R(0) : k_F * R(kx);     // qt_x of this plane
     // the W tile feeds U_x and U_y: with one phase-1 item per thread it is
     // read once, into registers (line tid % TZ, elements tid / TZ + R2 m);
@@ -655,10 +727,11 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
         const int it = tid;
         const bool ok = (ITEMS % NT == 0) || it < ITEMS;
         const int line = it % TZ, t = it / TZ;
+        const unsigned lane_off = ok ? unsigned((t * N + line) * int(sizeof(C))) : kBufOutside;
 #pragma unroll
-        for (int m = 0; m < R1; ++m) zr[m] = ok ? z[long(t + R2 * m) * N + line] : cmk<C>(R(0), R(0));
+        for (int m = 0; m < R1; ++m) zr[m] = load_row(zlo, zhi, lane_off, t, m);
 #pragma unroll
-        for (int m = 0; m < R1; ++m) wr[0][m] = ok ? w[long(t + R2 * m) * N + line] : cmk<C>(R(0), R(0));
+        for (int m = 0; m < R1; ++m) wr[0][m] = load_row(wlo, whi, lane_off, t, m);
     }
     __syncthreads();                                        // twl
 #pragma unroll
@@ -686,9 +759,10 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
                 tp_phase1_item<C, N, +1, TZ, true>(v, line, t, lds, twl);
             }
         } else {
-            const C* src = j == 2 ? z : w;
-            auto ld = [&](int zz, int yy) -> C {
-                C v = src[long(yy) * N + zz];
+            auto ld = [&](int zz, int t, int m) -> C {
+                const int yy = t + R2 * m;
+                const unsigned lane_off = unsigned((t * N + zz) * int(sizeof(C)));
+                C v = j == 2 ? load_row(zlo, zhi, lane_off, t, m) : load_row(wlo, whi, lane_off, t, m);
                 if (j < 2) {
                     R q = qx;
                     if (j == 1) {
@@ -699,7 +773,7 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
                 }
                 return v;
             };
-            tp_phase1<C, N, +1, TZ, NT, true>(ld, lds, twl, tid);
+            tp_phase1_tm<C, N, +1, TZ, NT, true>(ld, lds, twl, tid);
         }
         __syncthreads();
         C* dst = T + (3 * al + j) * FS;
@@ -722,7 +796,9 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
 // LDS at about 52 KB, three blocks per CU, which hides more latency than a
 // second buffer would (measured).  The Hermitian extension of the x lines
 // is applied when phase 1 reads the tile back (the gradient factors were
-// applied by the earlier passes).
+// applied by the earlier passes).  Planes kx > kx_sup are outside the
+// support of every term: their part of the tile is zeroed once and never
+// loaded.
 // ----------------------------------------------------------------------------
 // x-pass schedule: TZX z values (TZX/2 pairs) per block, a part of one
 // gradient-field tile; threads: a divisor of the N TZX/2 point pairs, at
@@ -753,7 +829,7 @@ template <typename R, int N, int TZX_, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T* __restrict__ T_all, long t_stride,
                                                   const R* __restrict__ sigma, int a0, int na, R dV, R k_F,
                                                   typename CplxOf<R>::T* __restrict__ Q_all, long q_stride,
-                                                  int n_planes, int accumulate,
+                                                  int n_planes, int accumulate, int kx_sup,
                                                   const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using S = Shape<R, N>;
@@ -771,7 +847,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
     constexpr int NLI = 3 * P;                                   // inverse lines (field, z pair)
     constexpr int NRAW = 3 * H * P;                              // raw pairs per term
     constexpr int TRS = CMax<TPLayout<N, NLI, true>::size, NLI * LS>::v;
-    __shared__ C raw[2 * NRAW];                                  // [field][kx][pair][2]
+    __shared__ __align__(16) C raw[2 * NRAW];                    // [field][kx][pair][2]
     __shared__ C Z[TRS];                                         // transpose, then G lines
     __shared__ C twl[N];
     const int tid = threadIdx.x;
@@ -801,8 +877,12 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
     static_assert((3 * FS) * long(sizeof(C)) < (1L << 32), "tile offsets are 32-bit");
     const int lane = tid & 63;
     // byte offset of this lane's unit in each load round, relative to the
-    // term's first field: the same for every term
+    // term's first field: the same for every term; bit i of ld_mask: the
+    // unit of round i lies on a plane kx <= kx_sup (else it is zeroed here
+    // once and never loaded)
+    static_assert(NIT <= 32, "one mask bit per load round");
     unsigned uoff[NIT];
+    unsigned ld_mask = 0;
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const int u = tid + i * NT;
@@ -811,6 +891,8 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
         const int rem = e - j * (H * P);
         const int k = rem / P, p = rem - k * P;
         uoff[i] = unsigned((long(j) * FS + long(k) * TZT + 2 * p) * long(sizeof(C)) + 16 * h);
+        if (k <= kx_sup) ld_mask |= 1u << i;
+        else if (u < NU) reinterpret_cast<float4*>(raw)[u] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     auto issue_tile = [&](int a, C* dst) {
         const char* colf = reinterpret_cast<const char*>(col0 + long(3 * (a - a0)) * FS);
@@ -818,7 +900,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int u0 = tid - lane + i * NT;               // uniform in the wavefront
-            if (u0 < NU && (i < NIT - 1 || u0 + lane < NU)) {
+            if (u0 < NU && (i < NIT - 1 || u0 + lane < NU) && ((ld_mask >> i) & 1u)) {
                 // lane i of the wavefront lands at dstb + 16 (u0 + i)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(colf + uoff[i]),
                                                  (__attribute__((address_space(3))) void*)(dstb + 16L * u0), 16, 0,
@@ -1347,24 +1429,34 @@ template <typename R, int NN> struct EngineImpl final : Engine {
         k_lut<<<dim3(unsigned(n2max / 256 + 1)), dim3(256), 0, s>>>(n2max, k_F, k_target, k_lo, k_hi, edges,
                                                                     n_modes, lut_u, lut_shell);
     }
+    // highest kx plane inside the support bound: min(N/2, floor(sqrt(n2_sup)))
+    static int kx_sup_of(int n2_sup) {
+        long r = long(std::sqrt(double(n2_sup)));
+        while ((r + 1) * (r + 1) <= n2_sup) ++r;
+        while (r > 0 && r * r > n2_sup) --r;
+        return int(std::min<long>(r, NN / 2));
+    }
     void gen_z(const void* phi_hat, const int* sel, int nb, const int16_t* lut_u, const void* phi_tab, int n_alpha,
-               int a0, int na, double k_F, double inv_V, void* Sd, long s_stride, hipStream_t s) override {
-        const unsigned blocks = unsigned((long(S::H) * NN) / GCfg<R, NN>::RB);
+               int a0, int na, double k_F, double inv_V, void* Sd, long s_stride, int n2_sup,
+               hipStream_t s) override {
+        const unsigned blocks = unsigned((long(kx_sup_of(n2_sup) + 1) * NN) / GCfg<R, NN>::RB);
+        if (blocks == 0 || nb <= 0 || n2_sup < 0) return;
         k_gen_z<R, NN><<<dim3(blocks, unsigned(nb)), dim3(GCfg<R, NN>::NT), 0, s>>>(
             static_cast<const C*>(phi_hat), sel, lut_u, static_cast<const R*>(phi_tab), n_alpha, a0, na, R(k_F),
-            R(inv_V), static_cast<C*>(Sd), s_stride, tw);
+            R(inv_V), static_cast<C*>(Sd), s_stride, n2_sup, tw);
     }
-    void ypass3(const void* Sd, int na, int nb, long s_stride, void* T, long t_stride, double k_F,
+    void ypass3(const void* Sd, int na, int nb, long s_stride, void* T, long t_stride, double k_F, int n2_sup,
                 hipStream_t s) override {
-        const unsigned blocks = unsigned(long(na) * S::H * (NN / YCfg<R, NN>::TZ));
-        if (blocks == 0 || nb <= 0) return;
+        const int hs = kx_sup_of(n2_sup) + 1;
+        const unsigned blocks = unsigned(long(na) * hs * (NN / YCfg<R, NN>::TZ));
+        if (blocks == 0 || nb <= 0 || n2_sup < 0) return;
         k_ypass3<R, NN><<<dim3(blocks, unsigned(nb)), dim3(YCfg<R, NN>::NT), 0, s>>>(
-            static_cast<const C*>(Sd), s_stride, static_cast<C*>(T), t_stride, R(k_F), tw);
+            static_cast<const C*>(Sd), s_stride, static_cast<C*>(T), t_stride, R(k_F), n2_sup, hs, tw);
     }
     void xprod(const void* T, long t_stride, int nb, const void* sigma_tab, int a0, int na, double dV, double k_F,
-               void* Qx, long q_stride, int n_planes, int accumulate, hipStream_t s) override {
+               void* Qx, long q_stride, int n_planes, int accumulate, int kx_sup, hipStream_t s) override {
         xs_[xsel_].fn(static_cast<const C*>(T), t_stride, nb, static_cast<const R*>(sigma_tab), a0, na, R(dV),
-                      R(k_F), static_cast<C*>(Qx), q_stride, n_planes, accumulate, tw, s);
+                      R(k_F), static_cast<C*>(Qx), q_stride, n_planes, accumulate, std::min(kx_sup, NN / 2), tw, s);
     }
     int xprod_schedules() const override { return nxs_; }
     void xprod_schedule_info(int i, int* tzx, int* occ) const override {
@@ -1376,7 +1468,8 @@ template <typename R, int NN> struct EngineImpl final : Engine {
 
     // x-pass schedules compiled for this size: entry 0 is the default, the
     // others differ in chunk width (half, double) and blocks-per-CU target.
-    using XFn = void (*)(const C*, long, int, const R*, int, int, R, R, C*, long, int, int, const C*, hipStream_t);
+    using XFn = void (*)(const C*, long, int, const R*, int, int, R, R, C*, long, int, int, int, const C*,
+                         hipStream_t);
     struct XSched {
         int tzx, occ;
         XFn fn;
@@ -1385,11 +1478,11 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     int nxs_ = 0, xsel_ = 0;
     template <int TZX, int OCC>
     static void xlaunch(const C* T, long t_stride, int nb, const R* sigma, int a0, int na, R dV, R kF, C* Qx,
-                        long q_stride, int n_planes, int acc, const C* twd, hipStream_t s) {
+                        long q_stride, int n_planes, int acc, int kx_sup, const C* twd, hipStream_t s) {
         using X = XShape<R, NN, TZX>;
         const unsigned blocks = unsigned(NN * (NN / X::TZX));
         k_xprod<R, NN, TZX, OCC><<<dim3(blocks, unsigned(nb)), dim3(X::NTX), 0, s>>>(
-            T, t_stride, sigma, a0, na, dV, kF, Qx, q_stride, n_planes, acc, twd);
+            T, t_stride, sigma, a0, na, dV, kF, Qx, q_stride, n_planes, acc, kx_sup, twd);
     }
     template <int TZX, int OCC> void add_schedule() {
         using X = XShape<R, NN, TZX>;

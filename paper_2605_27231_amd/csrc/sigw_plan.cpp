@@ -396,6 +396,18 @@ bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n
     return true;
 }
 
+// Support bound of the weighted fields of target k: phi_a(u) vanishes for
+// u >= u_max (the last grid edge), so every mode that the interval lookup
+// maps into the grid has k_F |n| / k < u_max, i.e. |n|^2 < (u_max k / k_F)^2.
+// The relative margin covers the rounding of the lookup's FP64 u; a bound
+// above the true one only costs pruning, never correctness.
+int support_n2(const sigw_plan* p, double k_target) {
+    const double kF = 2.0 * kPi / p->d.L;
+    const double r = p->edges_h.back() * k_target / kF;
+    const double r2 = r * r * (1.0 + 1e-12) + 1.0;
+    return r2 >= double(p->z.n2max) ? int(p->z.n2max) : int(r2);
+}
+
 // Enqueue the convolutions of one target for nb realisations (the slots at
 // sel_dev[0..nb)), leaving each member's 12 components after the forward y
 // pass in its Q workspace (planes [0, n_planes)).
@@ -403,6 +415,8 @@ sigw_status enqueue_convolutions(sigw_plan* p, const int* sel_dev, int nb, doubl
     const sigw_plan_desc& d = p->d;
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / d.L;
+    const int n2_sup = support_n2(p, k_target);
+    const int kx_sup = std::min(int(z.H) - 1, (int)std::floor(std::sqrt((double)n2_sup)));
     const double V = d.L * d.L * d.L;
     const double dV = V / double(z.R3);
     const long s_stride = long(2) * z.stage * z.FS;
@@ -420,15 +434,17 @@ sigw_status enqueue_convolutions(sigw_plan* p, const int* sel_dev, int nb, doubl
                 void* Tdst = cplx_at(p->T, long(3) * (as - a0) * z.FS, z.cb);
                 s = timed(p, 0, [&] {
                     p->eng->gen_z(p->phi_hat, sel_dev, nb, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V,
-                                  p->Sst, s_stride, p->stream);
+                                  p->Sst, s_stride, n2_sup, p->stream);
                 });
                 if (s) return s;
-                s = timed(p, 1, [&] { p->eng->ypass3(p->Sst, ns, nb, s_stride, Tdst, t_stride, kF, p->stream); });
+                s = timed(p, 1, [&] {
+                    p->eng->ypass3(p->Sst, ns, nb, s_stride, Tdst, t_stride, kF, n2_sup, p->stream);
+                });
                 if (s) return s;
             }
             s = timed(p, 2, [&] {
                 p->eng->xprod(p->T, t_stride, nb, p->sigma_tab[m], a0, na, dV, kF, Qm, q_stride, n_planes,
-                              a0 > 0 ? 1 : 0, p->stream);
+                              a0 > 0 ? 1 : 0, kx_sup, p->stream);
             });
             if (s) return s;
         }
@@ -573,11 +589,13 @@ sigw_status tune_xprod(sigw_plan* p, int flags) {
     sigw_status st = SIGW_OK;
     for (int i = 0; i < n && st == SIGW_OK; ++i) {
         e->set_xprod_schedule(i);
-        e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, p->stream);
+        e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, int(z.H) - 1,
+                     p->stream);
         for (int r = 0; r < 3 && st == SIGW_OK; ++r) {
             float ms = 0.0f;
             if (hipEventRecord(e0, p->stream) != hipSuccess) st = SIGW_E_DEVICE;
-            e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, p->stream);
+            e->xprod(p->T, t_stride, 1, p->sigma_tab[0], 0, na, dV, kF, p->Q, q_stride, int(z.H), 0, int(z.H) - 1,
+                     p->stream);
             if (st == SIGW_OK && (hipEventRecord(e1, p->stream) != hipSuccess ||
                                   hipEventSynchronize(e1) != hipSuccess ||
                                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
