@@ -54,8 +54,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 // Layout of the gradient fields U (written by ypass3, read by xprod): tiles
 // of TZT z values, 128 bytes.  Element (kx, y, z) of a field sits at
-//   ((y * (N / TZT) + z / TZT) * (N/2 + 1) + kx) * TZT + z % TZT.
-// ypass3 writes whole 128-byte lines per (kx, y); the (N/2+1) x TZT region
+//   ((y * (N / TZT) + z / TZT) * hs + kx) * TZT + z % TZT,
+// hs = kx_sup + 1 the planes of the target's support (N/2 + 1 when it
+// covers the lattice): the written and read part of a field is one
+// contiguous block whatever the support.
+// ypass3 writes whole 128-byte lines per (kx, y); the hs x TZT region
 // that the xprod blocks of one (y, z tile) read together is contiguous.  At
 // 512^3 the x pass reads this about twice as fast as the kx-major
 // half-spectrum order, at 256^3 about as fast; 256- and 512-byte tiles and a
@@ -65,8 +68,8 @@ template <typename R, int N> struct TTile {
     static constexpr int TZT = TZT0 < N ? TZT0 : N;
 };
 template <int N, int TZT>
-__device__ __forceinline__ long t_offset(int kx, int y, int z) {
-    return ((long(y) * (N / TZT) + z / TZT) * (N / 2 + 1) + kx) * TZT + z % TZT;
+__device__ __forceinline__ long t_offset(int kx, int y, int z, int hs) {
+    return ((long(y) * (N / TZT) + z / TZT) * hs + kx) * TZT + z % TZT;
 }
 
 // Raw buffer loads of complex values.  The descriptor covers `bytes` bytes
@@ -529,9 +532,37 @@ __global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_tar
 // The x and y gradients are applied later (i qt_y before the y transform,
 // i qt_x in the x pass), so two fields per term cross HBM here, not three.
 // Rows outside the support (nx^2 + ny^2 > n2_sup) are zero for every term:
-// they are neither read nor written (ypass3 reads them as zeros), and the
-// grid covers only the planes kx <= kx_sup.
+// they are neither read nor written (ypass3 reads them as zeros).  Grid x =
+// term groups of tg terms x planes kx <= kx_sup x c0 row blocks, c0 the live
+// row blocks of plane 0 (the most of any plane); block j of plane kx takes
+// that plane's j-th live row block, if it has one.  A small support leaves
+// few live row blocks, and splitting the terms over blocks keeps the chip
+// busy (Phi_hat is then read once per group, a small fraction of the
+// writes).
 // ----------------------------------------------------------------------------
+// Largest y >= 0 with y^2 <= v (v >= 0), at most N/2: the largest live |ny|
+// of a row set bounded by ny^2 <= v.
+template <int N> __host__ __device__ inline int ylim_of(int v) {
+    int r = int(sqrt(double(v)));
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r < N / 2 ? r : N / 2;
+}
+// Row blocks (RB consecutive ky) of one kx plane that hold live rows, the
+// live rows being ky <= ylim and ky >= N - ylim: the first lc blocks and the
+// last uc, or all N/RB when the two runs meet.
+template <int N, int RB> __host__ __device__ inline int live_row_blocks(int ylim) {
+    const int lc = ylim / RB + 1;
+    const int uc = ylim > 0 ? N / RB - (N - ylim) / RB : 0;
+    return lc + uc >= N / RB ? N / RB : lc + uc;
+}
+template <int N, int RB> __host__ __device__ inline int live_row_block(int ylim, int j) {
+    const int lc = ylim / RB + 1;
+    const int uc = ylim > 0 ? N / RB - (N - ylim) / RB : 0;
+    if (lc + uc >= N / RB) return j;
+    return j < lc ? j : N / RB - uc + (j - lc);
+}
+
 template <typename R, int N> struct GCfg {
     static constexpr int R1 = TPConst<N>::R1;
     static constexpr int R2 = TPConst<N>::R2;
@@ -545,7 +576,8 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
                                                const int* __restrict__ sel, const int16_t* __restrict__ lut_u,
                                                const R* __restrict__ phi_tab, int n_alpha, int a0, int na, R k_F,
                                                R inv_V, typename CplxOf<R>::T* __restrict__ S_all, long s_stride,
-                                               int n2_sup, const typename CplxOf<R>::T* __restrict__ tw) {
+                                               int n2_sup, int c0, int nrb, int tg,
+                                               const typename CplxOf<R>::T* __restrict__ tw) {
     using C = typename CplxOf<R>::T;
     using G = GCfg<R, N>;
     constexpr int RB = G::RB, NT = G::NT, R1 = G::R1, R2 = G::R2;
@@ -557,7 +589,13 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
     __shared__ C lds[Lay::size];
     static_assert(N % RB == 0 && RB <= 32, "the rows of a block share one kx plane");
     const int tid = threadIdx.x;
-    const long row0 = long(blockIdx.x) * RB;
+    const int rem = int(blockIdx.x % nrb);
+    const int kxb = rem / c0, jb = rem % c0;
+    const int ylb = ylim_of<N>(n2_sup - kxb * kxb);
+    if (jb >= live_row_blocks<N, RB>(ylb)) return;           // uniform over the block
+    const long row0 = long(kxb) * N + long(live_row_block<N, RB>(ylb, jb)) * RB;
+    const int ab = a0 + int(blockIdx.x / nrb) * tg;       // this block's terms [ab, ae)
+    const int ae = ab + tg < a0 + na ? ab + tg : a0 + na;
     // rows of this block inside the support: bit row of live
     unsigned live = 0;
     {
@@ -594,7 +632,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
             idx[i][m] = ok ? lut_u[nx * nx + ny * ny + nz * nz] : int16_t(-1);
         }
     }
-    for (int a = a0; a < a0 + na; ++a) {
+    for (int a = ab; a < ae; ++a) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int w = tid + i * NT;
@@ -777,7 +815,7 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
         }
         __syncthreads();
         C* dst = T + (3 * al + j) * FS;
-        auto st = [&](int zz, int y, C v) { dst[t_offset<N, TZT>(kx, y, zc * TZ + zz)] = v; };
+        auto st = [&](int zz, int y, C v) { dst[t_offset<N, TZT>(kx, y, zc * TZ + zz, hs)] = v; };
         tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tid);
         __syncthreads();
     }
@@ -868,7 +906,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
     // z values per kx, TZT apart
     constexpr int TZT = TTile<R, N>::TZT;
     static_assert(TZT % TZ == 0, "an x-pass chunk lies inside one field tile");
-    const C* col0 = T + t_offset<N, TZT>(0, y, z0);
+    const C* col0 = T + t_offset<N, TZT>(0, y, z0, kx_sup + 1);
     // 16-byte units: a raw element (two complex) is 1 unit in FP32, 2 in FP64
     constexpr int UPE = int(2 * sizeof(C) / 16);
     constexpr int NU = NRAW * UPE;
@@ -1439,11 +1477,22 @@ template <typename R, int NN> struct EngineImpl final : Engine {
     void gen_z(const void* phi_hat, const int* sel, int nb, const int16_t* lut_u, const void* phi_tab, int n_alpha,
                int a0, int na, double k_F, double inv_V, void* Sd, long s_stride, int n2_sup,
                hipStream_t s) override {
-        const unsigned blocks = unsigned((long(kx_sup_of(n2_sup) + 1) * NN) / GCfg<R, NN>::RB);
-        if (blocks == 0 || nb <= 0 || n2_sup < 0) return;
-        k_gen_z<R, NN><<<dim3(blocks, unsigned(nb)), dim3(GCfg<R, NN>::NT), 0, s>>>(
+        constexpr int RB = GCfg<R, NN>::RB;
+        if (nb <= 0 || na <= 0 || n2_sup < 0) return;
+        const int kxs = kx_sup_of(n2_sup);
+        const int c0 = live_row_blocks<NN, RB>(ylim_of<NN>(n2_sup));
+        const int nrb = (kxs + 1) * c0;
+        long live = 0;                                       // live row blocks of all planes
+        for (int kx = 0; kx <= kxs; ++kx) live += live_row_blocks<NN, RB>(ylim_of<NN>(n2_sup - kx * kx));
+        // about 4096 busy blocks per launch (16 per CU) when the support allows
+        constexpr long kBusy = 4096;
+        const long want = (kBusy + live * nb - 1) / std::max(1L, live * nb);
+        const int ng0 = int(std::min<long>(std::max<long>(want, 1), na));
+        const int tg = (na + ng0 - 1) / ng0;
+        const int ng = (na + tg - 1) / tg;
+        k_gen_z<R, NN><<<dim3(unsigned(long(nrb) * ng), unsigned(nb)), dim3(GCfg<R, NN>::NT), 0, s>>>(
             static_cast<const C*>(phi_hat), sel, lut_u, static_cast<const R*>(phi_tab), n_alpha, a0, na, R(k_F),
-            R(inv_V), static_cast<C*>(Sd), s_stride, n2_sup, tw);
+            R(inv_V), static_cast<C*>(Sd), s_stride, n2_sup, c0, nrb, tg, tw);
     }
     void ypass3(const void* Sd, int na, int nb, long s_stride, void* T, long t_stride, double k_F, int n2_sup,
                 hipStream_t s) override {
