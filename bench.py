@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on `bench.py --quick`,
 # scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
 # source they were taken on (see the summaries in profiles/).
-COUNTER_SOURCE_SHA = "2b11115b1ab3bde5"
-COUNTER_TRAFFIC = {"xprod": 33078903830.1, "ypass": 51249631772.7, "gen_z": 19059039185.7}
+COUNTER_SOURCE_SHA = "322026963ebfbfd7"
+COUNTER_TRAFFIC = {"xprod": 33060384350.4, "ypass": 51248870081.4, "gen_z": 19068918299.8}
 
 
 def kernel_source_sha() -> str:
