@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "sigw_engine.hpp"
 #include "sigw_fft.hpp"
@@ -608,6 +609,10 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
         }
     }
     if (live == 0) return;                                  // uniform over the block
+    // FULL: every row of the block is live (the common case), and the row
+    // predicates drop out of the compiled form
+    auto run = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
     // batch member blockIdx.y works on the realisation in slot sel[blockIdx.y]
     const C* phi_hat = phi_hat_all + long(sel[blockIdx.y]) * FS;
     C* T = S_all + blockIdx.y * s_stride;
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
         const int w = tid + i * NT;
         const bool inr = (ITEMS % NT == 0) || w < ITEMS;
         const int row = inr ? w / R2 : 0;
-        const bool ok = inr && ((live >> row) & 1u);
+        const bool ok = inr && (FULL || ((live >> row) & 1u));
         const int t = ok ? w % R2 : 0;
         const long r = row0 + row;
         const int kx = int(r / N), ky = int(r % N);
@@ -671,11 +676,15 @@ __global__ __launch_bounds__(256) void k_gen_z(const typename CplxOf<R>::T* __re
         const long fbase = long(2 * (a - a0)) * FS;
         auto st = [&](int line, int kz, C v) {
             const int j = line / RB, row = line % RB;
-            if ((live >> row) & 1u) T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
+            if (FULL || ((live >> row) & 1u)) T[fbase + long(j) * FS + (row0 + row) * N + kz] = v;
         };
         tp_phase2<C, N, +1, NL, NT, false>(st, lds, tid);
         __syncthreads();
     }
+    };
+    constexpr unsigned kAll = RB == 32 ? 0xffffffffu : (1u << RB) - 1u;
+    if (live == kAll) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 // ----------------------------------------------------------------------------
