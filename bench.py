@@ -87,35 +87,55 @@ def support_n2(N: int, L: float, k: float, u_max: float) -> int:
     return n2max if r2 >= n2max else int(r2)
 
 
+GRID_SIZES = (8, 16, 32, 64, 128, 256, 384, 512)
+
+
+def target_grid(N: int, L: float, k: float, u_max: float, n2_hi: int) -> int:
+    """The lattice a target's convolutions run on, as the library picks it:
+    the smallest compiled size M with M > 2 Rc + Kc and M > 2 Kc + 1 (Rc, Kc:
+    largest |n_c| of the weighted fields' support and of the shell), if it
+    is below N; else N."""
+    rc = math.isqrt(support_n2(N, L, k, u_max))
+    kc = math.isqrt(n2_hi)
+    need = max(2 * rc + kc + 1, 2 * kc + 2)
+    if need >= N:
+        return N
+    return next((m for m in GRID_SIZES if need <= m < N), N)
+
+
 def algorithmic_bytes(N: int, L: float, cb: int, n_alpha: int, u_max: float, targets, k_lo, k_hi):
     """Compulsory HBM bytes per launch of each hot kernel (each input read
     once, each output written once), averaged over the launches of one
     spectrum: one launch per target with modes and kernel m (gen_z and
-    ypass3: one per staged group of st terms).  Only the support of the
-    weighted fields counts: rows (kx, ky) with nx^2 + ny^2 <= n2_sup after
-    the z pass, planes kx <= kx_sup after the y pass; everything outside is
-    zero and is neither read nor written."""
-    H = N // 2 + 1
-    plane = N * N
-    st = stage_terms(N, cb, n_alpha)
-    groups = [min(st, n_alpha - a) for a in range(0, n_alpha, st)]
-    ny2 = np.fft.fftfreq(N, 1.0 / N) ** 2
+    ypass3: one per staged group of st terms), on the lattice the target
+    runs on (target_grid).  Only the support of the weighted fields counts:
+    rows (kx, ky) with nx^2 + ny^2 <= n2_sup after the z pass, planes
+    kx <= kx_sup after the y pass; everything outside is zero and is neither
+    read nor written."""
+    st_n = stage_terms(N, cb, n_alpha)
     tot = {"gen_z": 0.0, "ypass": 0.0, "xprod": 0.0}
     cnt = {"gen_z": 0, "ypass": 0, "xprod": 0}
     for kt, lo, hi in zip(targets, k_lo, k_hi):
         n2_hi = shell_n2_hi(N, L, lo, hi)
         if n2_hi is None:
             continue                                   # empty shell: no launches
-        n2s = support_n2(N, L, kt, u_max)
+        M = target_grid(N, L, kt, u_max, n2_hi)
+        H = M // 2 + 1
+        plane = M * M
+        # a smaller grid stages more terms in the same buffer
+        st = st_n if M == N else min(n_alpha, st_n * ((N // 2 + 1) * N * N) // (H * plane))
+        groups = [min(st, n_alpha - a) for a in range(0, n_alpha, st)]
+        n2s = min(support_n2(N, L, kt, u_max), 3 * (M // 2) ** 2)
         kxs = min(H - 1, math.isqrt(n2s))
         n_planes = min(H - 1, math.isqrt(n2_hi)) + 1
+        ny2 = np.fft.fftfreq(M, 1.0 / M) ** 2
         kx2 = np.arange(kxs + 1)[:, None] ** 2
         rows = int(((kx2 + ny2[None, :]) <= n2s).sum())   # live (kx, ky) rows
         for g in groups:
             # reads Phi_hat on the live rows, writes the (W, Z) pair of each term there
-            tot["gen_z"] += (rows * N + 2 * g * rows * N) * cb
+            tot["gen_z"] += (rows * M + 2 * g * rows * M) * cb
             # reads the live rows of the pairs, writes 3 gradient fields per term on kx <= kx_sup
-            tot["ypass"] += (2 * g * rows * N + 3 * g * (kxs + 1) * plane) * cb
+            tot["ypass"] += (2 * g * rows * M + 3 * g * (kxs + 1) * plane) * cb
             cnt["gen_z"] += 1
             cnt["ypass"] += 1
         # reads the 3 n_alpha gradient fields on kx <= kx_sup, writes 6 components on the shell's planes

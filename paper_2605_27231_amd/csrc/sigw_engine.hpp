@@ -50,6 +50,13 @@ struct Engine {
     virtual void laplacian(void* half, double c, hipStream_t s) = 0;
     virtual void square(const void* in, void* out, hipStream_t s) = 0;
     virtual void nonlocal_combine(const void* zg, const void* l1, const void* l2, void* out, hipStream_t s) = 0;
+    // Half spectrum of this (smaller) grid taken from half spectra of an
+    // n_src grid: dst[b] gets slot sel[b] of src at every mode of this grid
+    // (signed indices |n_y|, |n_z| <= N/2, the index -N/2 read at n = -N/2 of
+    // the source).  Exact copies; the caller ensures the field it serves has
+    // no support outside |n_c| < N/2.
+    virtual void restrict_half(const void* src, int n_src, const int* sel, int nb, void* dst,
+                               hipStream_t s) = 0;
     // Per-target tables over integer |n|^2 in [0, 3 (N/2)^2]: u-interval index
     // of u = k_F sqrt(n2) / k_target (-1 outside) and shell membership
     // k_lo <= k_F sqrt(n2) < k_hi, n2 > 0.

@@ -500,6 +500,26 @@ __global__ __launch_bounds__(256) void k_map_scale(const R* __restrict__ in, R* 
 }
 
 // ----------------------------------------------------------------------------
+// Half spectrum of an N grid from half spectra of a larger n_src grid (the
+// same box): every mode of the N grid, by signed index, copied from the
+// source.  Used for targets whose convolution fits a smaller grid exactly.
+// ----------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_restrict(const typename CplxOf<R>::T* __restrict__ src, int n_src,
+                                                  const int* __restrict__ sel,
+                                                  typename CplxOf<R>::T* __restrict__ dst) {
+    constexpr long FS = Shape<R, N>::FS;
+    const long i = long(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= FS) return;
+    const int kx = int(i / (long(N) * N));
+    const int ky = int((i / N) % N), kz = int(i % N);
+    const int ny = signed_index(ky, N), nz = signed_index(kz, N);
+    const long sy = ny < 0 ? ny + n_src : ny, sz = nz < 0 ? nz + n_src : nz;
+    const long fs_src = long(n_src / 2 + 1) * n_src * n_src;
+    dst[long(blockIdx.y) * FS + i] = src[long(sel[blockIdx.y]) * fs_src + (long(kx) * n_src + sy) * n_src + sz];
+}
+
+// ----------------------------------------------------------------------------
 // Per-target lookup tables over integer |n|^2.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_lut(int n2max, double k_F, double k_target, double k_lo, double k_hi,
@@ -1469,6 +1489,11 @@ template <typename R, int NN> struct EngineImpl final : Engine {
         const long total = long(NN) * NN * NN;
         k_map_scale<R><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(
             static_cast<const R*>(in), static_cast<R*>(out), total, sum_sq, mp, scale);
+    }
+    void restrict_half(const void* src, int n_src, const int* sel, int nb, void* dst, hipStream_t s) override {
+        if (nb <= 0 || n_src <= NN) return;
+        k_restrict<R, NN><<<dim3(unsigned((S::FS + 255) / 256), unsigned(nb)), dim3(256), 0, s>>>(
+            static_cast<const C*>(src), n_src, sel, static_cast<C*>(dst));
     }
     void lut(double k_F, double k_target, double k_lo, double k_hi, const double* edges, int n_modes,
              int16_t* lut_u, uint8_t* lut_shell, hipStream_t s) override {

@@ -238,6 +238,8 @@ Sizes sizes_of(const sigw_plan_desc& d) {
 }
 
 constexpr int kMaxTargets = 4096;
+// lattice sizes the kernels are compiled for
+constexpr int kGridSizes[] = {8, 16, 32, 64, 128, 256, 384, 512};
 constexpr int kSumsqBlocks = 1024;
 
 size_t footprint_of(const sigw_plan_desc& d) {
@@ -255,6 +257,13 @@ size_t footprint_of(const sigw_plan_desc& d) {
     b += size_t(z.R3) * z.rb;                                  // real scratch
     b += size_t(z.batch) * zb * 16 + size_t(kSumsqBlocks + 1) * 8;   // partials
     b += size_t(kMaxTargets) * (16 + 4);                       // per-target sums, slot list
+    long fs_c = 0;                                             // coarse grids: twiddles, Phi_hat copies
+    for (int m : kGridSizes)
+        if (m < d.N) {
+            b += size_t(m) * z.cb;
+            fs_c = long(m / 2 + 1) * m * m;
+        }
+    b += size_t(z.batch) * (size_t(fs_c) * z.cb + 4);
     return b;
 }
 
@@ -269,6 +278,16 @@ struct sigw_plan {
     hipStream_t stream = nullptr;
     int device = 0;
     std::unique_ptr<sigw::Engine> eng;
+    // smaller grids of the same box, for targets whose convolution one of
+    // them computes exactly (increasing size, all below d.N)
+    struct Coarse {
+        int N = 0;
+        void* tw = nullptr;
+        std::unique_ptr<sigw::Engine> eng;
+    };
+    std::vector<Coarse> coarse;
+    void* phi_c = nullptr;      // batch x half spectrum of the largest coarse grid
+    int* d_iota = nullptr;      // 0, 1, ..., batch - 1
     std::string err;
     std::string schedule;       // report of the active x-pass schedule
     std::vector<double> edges_h;
@@ -400,56 +419,104 @@ bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n
 // u >= u_max (the last grid edge), so every mode that the interval lookup
 // maps into the grid has k_F |n| / k < u_max, i.e. |n|^2 < (u_max k / k_F)^2.
 // The relative margin covers the rounding of the lookup's FP64 u; a bound
-// above the true one only costs pruning, never correctness.
-int support_n2(const sigw_plan* p, double k_target) {
+// above the true one only costs pruning, never correctness.  Capped at the
+// largest |n|^2 of the lattice (n2max).
+int support_n2(const sigw_plan* p, double k_target, long n2max) {
     const double kF = 2.0 * kPi / p->d.L;
     const double r = p->edges_h.back() * k_target / kF;
     const double r2 = r * r * (1.0 + 1e-12) + 1.0;
-    return r2 >= double(p->z.n2max) ? int(p->z.n2max) : int(r2);
+    return r2 >= double(n2max) ? int(n2max) : int(r2);
 }
 
-// Enqueue the convolutions of one target for nb realisations (the slots at
-// sel_dev[0..nb)), leaving each member's 12 components after the forward y
-// pass in its Q workspace (planes [0, n_planes)).
-sigw_status enqueue_convolutions(sigw_plan* p, const int* sel_dev, int nb, double k_target, int n_planes) {
+int isqrt_floor(long v) {
+    long r = long(std::sqrt(double(v)));
+    while (r > 0 && r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return int(r);
+}
+
+// The lattice one target's convolutions run on: the plan's own, or a smaller
+// grid of the same box (same k_F).  Phi_hat of member b is at phi + sel[b] FS.
+struct Grid {
+    sigw::Engine* e;
+    int N;
+    long FS, H, n2max;
+    int stage;                  // terms staged per gen_z / ypass3 pair
+    const void* phi;
+    const int* sel;
+};
+
+Grid own_grid(sigw_plan* p, const int* sel_dev) {
+    const Sizes& z = p->z;
+    return Grid{p->eng.get(), p->d.N, z.FS, z.H, z.n2max, z.stage, p->phi_hat, sel_dev};
+}
+
+// Enqueue the convolutions of one target for nb realisations on grid g,
+// leaving each member's 12 components after the forward y pass in its Q
+// workspace (component c at c g.FS, planes [0, n_planes)).  The member
+// strides of the workspaces are the plan's (a smaller grid fits inside).
+sigw_status enqueue_convolutions_on(sigw_plan* p, const Grid& g, int nb, double k_target, int n_planes) {
     const sigw_plan_desc& d = p->d;
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / d.L;
-    const int n2_sup = support_n2(p, k_target);
-    const int kx_sup = std::min(int(z.H) - 1, (int)std::floor(std::sqrt((double)n2_sup)));
+    const int n2_sup = support_n2(p, k_target, g.n2max);
+    const int kx_sup = std::min(int(g.H) - 1, isqrt_floor(n2_sup));
     const double V = d.L * d.L * d.L;
-    const double dV = V / double(z.R3);
+    const double dV = V / (double(g.N) * g.N * g.N);
     const long s_stride = long(2) * z.stage * z.FS;
     const long t_stride = long(3) * z.chunk * z.FS;
     const long q_stride = long(12) * z.FS;
     for (int m = 0; m < 2; ++m) {
-        void* Qm = cplx_at(p->Q, long(m) * 6 * z.FS, z.cb);
+        void* Qm = cplx_at(p->Q, long(m) * 6 * g.FS, z.cb);
         for (int a0 = 0; a0 < d.n_alpha; a0 += z.chunk) {
             const int na = std::min(z.chunk, d.n_alpha - a0);
             sigw_status s;
             // stage a few terms at a time: their (W, Z) pairs are expanded
             // into gradient fields before the next group is generated
-            for (int as = a0; as < a0 + na; as += z.stage) {
-                const int ns = std::min(z.stage, a0 + na - as);
-                void* Tdst = cplx_at(p->T, long(3) * (as - a0) * z.FS, z.cb);
+            for (int as = a0; as < a0 + na; as += g.stage) {
+                const int ns = std::min(g.stage, a0 + na - as);
+                void* Tdst = cplx_at(p->T, long(3) * (as - a0) * g.FS, z.cb);
                 s = timed(p, 0, [&] {
-                    p->eng->gen_z(p->phi_hat, sel_dev, nb, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V,
-                                  p->Sst, s_stride, n2_sup, p->stream);
+                    g.e->gen_z(g.phi, g.sel, nb, p->lut_u, p->phi_tab[m], d.n_alpha, as, ns, kF, 1.0 / V, p->Sst,
+                               s_stride, n2_sup, p->stream);
                 });
                 if (s) return s;
                 s = timed(p, 1, [&] {
-                    p->eng->ypass3(p->Sst, ns, nb, s_stride, Tdst, t_stride, kF, n2_sup, p->stream);
+                    g.e->ypass3(p->Sst, ns, nb, s_stride, Tdst, t_stride, kF, n2_sup, p->stream);
                 });
                 if (s) return s;
             }
             s = timed(p, 2, [&] {
-                p->eng->xprod(p->T, t_stride, nb, p->sigma_tab[m], a0, na, dV, kF, Qm, q_stride, n_planes,
-                              a0 > 0 ? 1 : 0, kx_sup, p->stream);
+                g.e->xprod(p->T, t_stride, nb, p->sigma_tab[m], a0, na, dV, kF, Qm, q_stride, n_planes,
+                           a0 > 0 ? 1 : 0, kx_sup, p->stream);
             });
             if (s) return s;
         }
     }
-    return timed(p, 3, [&] { p->eng->ypass(p->Q, 12, z.FS, n_planes, -1, nb, q_stride, p->stream); });
+    return timed(p, 3, [&] { g.e->ypass(p->Q, 12, g.FS, n_planes, -1, nb, q_stride, p->stream); });
+}
+
+sigw_status enqueue_convolutions(sigw_plan* p, const int* sel_dev, int nb, double k_target, int n_planes) {
+    return enqueue_convolutions_on(p, own_grid(p, sel_dev), nb, k_target, n_planes);
+}
+
+// The smallest coarse grid that computes target k's shell sums exactly, or
+// -1.  The weighted fields have |n_c| <= Rc (support bound) and the shell
+// |n_c| <= Kc.  A product of two fields has |n_c| <= 2 Rc, so on an M grid
+// with M > 2 Rc + Kc no product mode aliases onto a shell mode, and with
+// M > 2 Kc + 1 every shell mode has its own index, off the kz = M/2 plane:
+// the circular convolution on the M grid then equals the linear one on the
+// shell, and so does the plan's (which needs N > 2 Rc + Kc itself: below
+// that, aliasing is part of its result and no smaller grid can reproduce
+// it).  The results agree up to rounding.
+int coarse_grid_for(const sigw_plan* p, double k_target, int n2_hi) {
+    const int Rc = isqrt_floor(support_n2(p, k_target, p->z.n2max));
+    const int Kc = isqrt_floor(n2_hi);
+    const long need = std::max<long>(2L * Rc + Kc + 1, 2L * Kc + 2);
+    if (need >= p->d.N) return -1;
+    for (size_t i = 0; i < p->coarse.size(); ++i)
+        if (p->coarse[i].N >= need) return int(i);
+    return -1;
 }
 
 // Stage a host slot list into the device slot list (pinned copy, no sync
@@ -491,30 +558,42 @@ sigw_status check_targets(sigw_plan* p, int n_k, const double* kt, const double*
 // empty shell.
 sigw_status enqueue_spectrum(sigw_plan* p, const int* sel_dev, int n_sel, int n_k, const double* kt,
                              const double* lo, const double* hi, double* sums, unsigned long long* cnts,
-                             std::vector<int>& valid) {
+                             std::vector<int>& valid, bool own_grid_only) {
     const sigw_plan_desc& d = p->d;
     const Sizes& z = p->z;
     const double kF = 2.0 * kPi / d.L;
     valid.assign(n_k, 0);
-    const int zb = p->eng->zbin_blocks();
     for (int b = 0; b < n_k; ++b) {
         int n2_lo = 0, n2_hi = -1;
         if (!shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi)) continue;
         valid[b] = 1;
-        const int kxm = std::min(d.N / 2, (int)std::floor(std::sqrt((double)n2_hi)));
+        // the plan's lattice, or the smallest grid that gives the same sums
+        const int ci = own_grid_only ? -1 : coarse_grid_for(p, kt[b], n2_hi);
+        const int gN = ci < 0 ? d.N : p->coarse[ci].N;
+        const int kxm = std::min(gN / 2, isqrt_floor(n2_hi));
         const int n_planes = kxm + 1;
+        // the tables cover the plan's |n|^2 range, which contains any smaller grid's
         p->eng->lut(kF, kt[b], lo[b], hi[b], p->edges, d.n_modes, p->lut_u, p->lut_shell, p->stream);
         for (int g0 = 0; g0 < n_sel; g0 += z.batch) {
             const int nb = std::min(z.batch, n_sel - g0);
-            sigw_status s = enqueue_convolutions(p, sel_dev + g0, nb, kt[b], n_planes);
+            Grid g = own_grid(p, sel_dev + g0);
+            if (ci >= 0) {
+                sigw::Engine* e = p->coarse[ci].eng.get();
+                const long H = gN / 2 + 1, FS = H * gN * long(gN);
+                // the (W, Z) pairs of more terms fit the staging buffer on a smaller grid
+                const int stage = int(std::min<long>(z.chunk, long(z.stage) * z.FS / FS));
+                g = Grid{e, gN, FS, H, 3L * (gN / 2) * (gN / 2), stage, p->phi_c, p->d_iota};
+                e->restrict_half(p->phi_hat, d.N, sel_dev + g0, nb, p->phi_c, p->stream);
+            }
+            sigw_status s = enqueue_convolutions_on(p, g, nb, kt[b], n_planes);
             if (s) return s;
             s = timed(p, 4, [&] {
-                p->eng->zbin(p->Q, nb, long(12) * z.FS, p->lut_shell, n2_lo, n2_hi, p->part_sum, p->part_cnt,
-                             p->stream);
+                g.e->zbin(p->Q, nb, long(12) * z.FS, p->lut_shell, n2_lo, n2_hi, p->part_sum, p->part_cnt,
+                          p->stream);
             });
             if (s) return s;
-            p->eng->finalize(p->part_sum, p->part_cnt, zb, nb, sums + long(g0) * n_k + b,
-                             cnts + long(g0) * n_k + b, n_k, p->stream);
+            g.e->finalize(p->part_sum, p->part_cnt, g.e->zbin_blocks(), nb, sums + long(g0) * n_k + b,
+                          cnts + long(g0) * n_k + b, n_k, p->stream);
         }
     }
     return check_launch(p);
@@ -694,6 +773,10 @@ sigw_status sigw_plan_destroy(sigw_plan_t p) {
                     p->part_cnt, p->sq_part, p->sums, p->cnts, p->d_sel};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (auto& c : p->coarse)
+        if (c.tw) (void)hipFree(c.tw);
+    if (p->phi_c) (void)hipFree(p->phi_c);
+    if (p->d_iota) (void)hipFree(p->d_iota);
     if (p->h_amp) (void)hipHostFree(p->h_amp);
     if (p->amp_ev) (void)hipEventDestroy(p->amp_ev);
     if (p->h_sel) (void)hipHostFree(p->h_sel);
@@ -801,6 +884,41 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
     if (!P->eng) {
         sigw_plan_destroy(p.release());
         return SIGW_E_UNSUPPORTED;
+    }
+    // coarse grids: an engine and a twiddle table each, one Phi_hat copy per
+    // batch member at the largest, and the member index list
+    long fs_c = 0;
+    for (int m : kGridSizes) {
+        if (m >= d->N) break;
+        sigw_plan::Coarse c;
+        c.N = m;
+        std::vector<char> tw(size_t(m) * z.cb);
+        sigw::host_twiddles(d->prec, m, tw.data());
+        if (!alloc(&c.tw, tw.size()) ||
+            hipMemcpy(c.tw, tw.data(), tw.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            P->coarse.push_back(std::move(c));
+            sigw_plan_destroy(p.release());
+            return SIGW_E_NOMEM;
+        }
+        c.eng.reset(sigw::make_engine(d->prec, m, c.tw));
+        const bool made = bool(c.eng);
+        P->coarse.push_back(std::move(c));
+        if (!made) {
+            sigw_plan_destroy(p.release());
+            return SIGW_E_UNSUPPORTED;
+        }
+        fs_c = long(m / 2 + 1) * m * m;
+    }
+    {
+        std::vector<int> iota(z.batch);
+        for (int i = 0; i < z.batch; ++i) iota[i] = i;
+        const bool okc = (fs_c == 0 || alloc(&P->phi_c, size_t(z.batch) * fs_c * z.cb)) &&
+                         alloc((void**)&P->d_iota, size_t(z.batch) * 4) &&
+                         hipMemcpy(P->d_iota, iota.data(), iota.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+        if (!okc) {
+            sigw_plan_destroy(p.release());
+            return SIGW_E_NOMEM;
+        }
     }
     P->schedule = schedule_name(P->eng.get(), 0);
     if (d->autotune) {
@@ -963,7 +1081,8 @@ sigw_status sigw_spectrum_batch(sigw_plan_t p, int32_t n_sel, const int32_t* slo
         if (sigw_status s = check_slot(p, slots[i], true)) return s;
     std::vector<int> valid;
     if (sigw_status s = upload_sel(p, slots, n_sel)) return s;
-    if (sigw_status s = enqueue_spectrum(p, p->d_sel, n_sel, n_k, kt, lo, hi, p->sums, p->cnts, valid)) return s;
+    if (sigw_status s = enqueue_spectrum(p, p->d_sel, n_sel, n_k, kt, lo, hi, p->sums, p->cnts, valid, false))
+        return s;
     const size_t cnt = size_t(n_sel) * n_k;
     if (cnt) {
         HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, cnt * 8, hipMemcpyDeviceToHost, p->stream));
@@ -1001,7 +1120,9 @@ sigw_status sigw_spectrum_jackknife(sigw_plan_t p, int32_t slot, int32_t n_k, co
     if (sigw_status s = upload_sel(p, &slot, 1)) return s;
     for (int b = 0; b < n_k; ++b) {
         std::vector<int> valid;
-        if (sigw_status s = enqueue_spectrum(p, p->d_sel, 1, 1, kt + b, lo + b, hi + b, p->sums, p->cnts, valid))
+        // the replicas need the shell's modes on the plan's own lattice
+        if (sigw_status s =
+                enqueue_spectrum(p, p->d_sel, 1, 1, kt + b, lo + b, hi + b, p->sums, p->cnts, valid, true))
             return s;
         double* S_i = p->part_sum;     // after finalize has consumed the zbin partials
         if (valid[0]) {
@@ -1112,7 +1233,8 @@ sigw_status sigw_spectrum_enqueue(sigw_plan_t p, int32_t slot, int32_t n_k, cons
     if (sigw_status s = check_targets(p, n_k, kt, lo, hi)) return s;
     if (sigw_status s = check_slot(p, slot, true)) return s;
     if (sigw_status s = upload_sel(p, &slot, 1)) return s;
-    if (sigw_status s = enqueue_spectrum(p, p->d_sel, 1, n_k, kt, lo, hi, p->sums, p->cnts, p->pend_valid)) return s;
+    if (sigw_status s = enqueue_spectrum(p, p->d_sel, 1, n_k, kt, lo, hi, p->sums, p->cnts, p->pend_valid, false))
+        return s;
     if (n_k) {
         HIP_TRY(p, hipMemcpyAsync(p->h_sums, p->sums, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
         HIP_TRY(p, hipMemcpyAsync(p->h_cnts, p->cnts, size_t(n_k) * 8, hipMemcpyDeviceToHost, p->stream));
@@ -1218,7 +1340,8 @@ sigw_status sigw_graph_create(sigw_plan_t p, int32_t n_sel, const int32_t* slots
         sigw_graph_destroy(gr.release());
         return fail(p, SIGW_E_DEVICE, "hipStreamBeginCapture (a graph needs a non-null plan stream)");
     }
-    sigw_status s = enqueue_spectrum(p, gr->d_slots, n_sel, n_k, kt, lo, hi, gr->d_sums, gr->d_cnts, gr->valid);
+    sigw_status s =
+        enqueue_spectrum(p, gr->d_slots, n_sel, n_k, kt, lo, hi, gr->d_sums, gr->d_cnts, gr->valid, false);
     if (s == SIGW_OK) {
         if (hipMemcpyAsync(gr->h_sums, gr->d_sums, cnt * 8, hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
             hipMemcpyAsync(gr->h_cnts, gr->d_cnts, cnt * 8, hipMemcpyDeviceToHost, p->stream) != hipSuccess)

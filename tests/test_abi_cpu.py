@@ -105,12 +105,14 @@ def test_library_kernel_table_other_meta_parameters():
 
 def test_footprint_batch_and_tables_cache():
     """Each batch member brings its own workspace (gradient fields, staging,
-    Q); the Sec. V tables come back identical from the process-wide cache."""
+    Q, a copy of Phi_hat on the largest smaller grid (64^3 here) and its
+    index); the Sec. V tables come back identical from the process-wide
+    cache."""
     base = P.sigw_plan_footprint(P.plan_desc(128))
     four = P.sigw_plan_footprint(P.plan_desc(128, batch=4))
     fs, cb = 65 * 128 * 128, 8
     stage = max(1, min(50, (16 << 30) // (2 * fs * cb)))
-    per_member = (3 * 50 + 2 * stage + 12) * fs * cb
+    per_member = (3 * 50 + 2 * stage + 12) * fs * cb + 33 * 64 * 64 * cb + 4
     assert four - base == 3 * per_member + 3 * 65 * 128 * 16
     assert P.sigw_plan_footprint(P.plan_desc(128, autotune=1)) == base
     a = P.sigw_kernel_table(P.plan_desc(64), 1)

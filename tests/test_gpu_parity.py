@@ -243,3 +243,31 @@ def test_batch_async_chunking_and_determinism(tabs):
         pl.generate_field(0, 11, spec, W.NGMap("local", F_NL=1.0))
         one = pl.spectrum(0, t, lo, hi)[0]
     np.testing.assert_array_equal(one, alone[1])
+
+
+@pytest.mark.parametrize("N,prec,tol", [(32, "f64", 1e-10), (64, "f32", 1e-4)])
+def test_small_supports(tabs, N, prec, tol):
+    """Targets whose weighted fields live on a small ball |n| < u_max k_b / k_F
+    (u_max = 15): from |n| <= 1 (k_b = 0.07) through supports that end inside
+    one FFT radix block or straddle one, to the whole lattice; each with a
+    shell of its own and with a fixed shell at |n| = 1..2, so that the rows
+    and planes the hot path skips are exercised against the oracle, which
+    skips nothing."""
+    L = 2 * math.pi
+    ph = field.phi_hat(N, L, 4, W.Lognormal(1e-2, 0.7, 3.0), W.NGMap("local", F_NL=2.0))
+    if prec == "f32":
+        ph = ph.astype(np.complex64).astype(np.complex128)
+    kb = np.array([0.07, 0.0667, 0.1, 0.27, 0.55, 0.8, 1.05, 1.6, 2.2, 4.0])
+    targets = np.concatenate([kb, kb])
+    lo = np.concatenate([np.maximum(kb - 0.5, 0.5), np.full(kb.size, 0.5)])
+    hi = np.concatenate([np.maximum(kb + 0.5, 1.5), np.full(kb.size, 2.5)])
+    if N > 32:                       # own shells only: keeps the oracle's time down
+        targets, lo, hi = targets[:kb.size], lo[:kb.size], hi[:kb.size]
+    _say(f"small supports N={N} prec={prec}")
+    ref, nref = spectrum.omega_spectrum(ph, tabs[0], tabs[1], targets, lo, hi, L)
+    with P.Plan(N, prec=prec) as pl:
+        pl.set_phi_hat(0, torch.from_numpy(ph))
+        got, nb = pl.spectrum(0, targets, lo, hi)
+    assert np.all(nref > 0)
+    rel = _check_bins(got, nb, ref, nref, tol)
+    _say("max rel err per bin", rel.max())
