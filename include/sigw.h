@@ -173,6 +173,11 @@ sigw_status sigw_source_convolutions(sigw_plan_t plan, int32_t slot, double k_ta
  *   X^(s) = -(4/k_b^2) Q_hat^(s),  X^(c) = +(4/k_b^2) Q_hat^(c),
  *   Omega_b = k_b^3 S_b / (48 pi^2 V N_b),  N_b = number of modes in the shell.
  * Shells with no mode give Omega_b = 0, N_b = 0 and cost nothing.
+ * A target whose weighted fields (|n_c| <= Rc, phi_a vanishing for
+ * u >= u_max) and shell (|n_c| <= Kc) satisfy 2 Rc + Kc < M and 2 Kc + 1 < M
+ * for a compiled size M < N is computed on that smaller grid of the same box,
+ * where the circular convolution has no aliasing on the shell: the result is
+ * the lattice's up to rounding.
  * Writes omega_host[n_k] and nmodes_host[n_k] (either may be NULL) and
  * synchronises the plan stream. */
 sigw_status sigw_spectrum(sigw_plan_t plan, int32_t slot, int32_t n_k, const double* k_targets,
