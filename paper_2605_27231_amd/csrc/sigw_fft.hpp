@@ -201,8 +201,11 @@ template <> struct TwoPhase<512> { static constexpr int R1 = 16; };
 // plus padding).  The phases contain no barrier: the caller synchronises
 // between phase 1 and phase 2 and before the buffer is reused.
 // ----------------------------------------------------------------------------
-template <int N, int NL, bool LINE_FAST> struct TPLayout {
-    static constexpr int R1 = TwoPhase<N>::R1;
+// R1_ = 0 takes the size's default factorisation (TwoPhase), another value
+// a different first radix for the same N.
+template <int N, int NL, bool LINE_FAST, int R1_ = 0> struct TPLayout {
+    static constexpr int R1 = R1_ ? R1_ : TwoPhase<N>::R1;
+    static_assert(N % R1 == 0, "the first radix divides N");
     static constexpr int R2 = N / R1;
     // LINE_FAST rows of one k1 hold R2 * NL elements.  When NL is not a
     // multiple of 16, the 16 lanes the LDS serves together span two k1 rows;
@@ -220,9 +223,9 @@ template <int N, int NL, bool LINE_FAST> struct TPLayout {
 // element t + R2 m of line `line`; a is overwritten.  The inter-phase
 // twiddles tw[t k1] depend on the lane: with tw a copy of the table in LDS
 // they stay off the vector memory path.
-template <typename C, int N, int SIGN, int NL, bool LINE_FAST>
+template <typename C, int N, int SIGN, int NL, bool LINE_FAST, int R1_ = 0>
 __device__ __forceinline__ void tp_phase1_item(C* a, int line, int t, C* lds, const C* tw) {
-    using Lay = TPLayout<N, NL, LINE_FAST>;
+    using Lay = TPLayout<N, NL, LINE_FAST, R1_>;
     constexpr int R1 = Lay::R1;
     reg_dft<R1, SIGN>(a);
 #pragma unroll
@@ -256,9 +259,9 @@ __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* tw, int tid)
 
 // As tp_phase1, with ld(line, t, m) returning element t + R2 m of a line;
 // m is a constant once the loop is unrolled, so ld can branch on it freely.
-template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, int R1_ = 0, class LD>
 __device__ __forceinline__ void tp_phase1_tm(LD&& ld, C* lds, const C* tw, int tid) {
-    using Lay = TPLayout<N, NL, LINE_FAST>;
+    using Lay = TPLayout<N, NL, LINE_FAST, R1_>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = NL * R2;
 #pragma unroll
@@ -270,7 +273,7 @@ __device__ __forceinline__ void tp_phase1_tm(LD&& ld, C* lds, const C* tw, int t
             C a[R1];
 #pragma unroll
             for (int m = 0; m < R1; ++m) a[m] = ld(line, t, m);
-            tp_phase1_item<C, N, SIGN, NL, LINE_FAST>(a, line, t, lds, tw);
+            tp_phase1_item<C, N, SIGN, NL, LINE_FAST, R1_>(a, line, t, lds, tw);
         }
     }
 }
@@ -283,9 +286,9 @@ __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw,
     for (int i = tid; i < N; i += NT) twl[i] = tw[i];
 }
 
-template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class ST>
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, int R1_ = 0, class ST>
 __device__ __forceinline__ void tp_phase2(ST&& st, const C* lds, int tid) {
-    using Lay = TPLayout<N, NL, LINE_FAST>;
+    using Lay = TPLayout<N, NL, LINE_FAST, R1_>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = NL * R1;
 #pragma unroll

@@ -274,6 +274,10 @@ __global__ __launch_bounds__(256) void k_zpass(typename CplxOf<R>::T* __restrict
 template <typename R, int N> struct YCfg {
     static constexpr int TZ = Shape<R, N>::TZ;
     static constexpr int NT = CMin<256, CMax<64, TZ * TPConst<N>::RMIN>::v>::v;
+    // first radix of ypass3: from 384^3 on (FP32) a larger one leaves one
+    // phase-1 item per thread (TZ R2 = NT), so the W tile stays in registers
+    // for both of its rounds instead of being read twice
+    static constexpr int R1_3 = (sizeof(R) == 4 && N >= 384) ? N * TZ / NT : 0;
 };
 
 template <typename R, int N, int SIGN>
@@ -732,7 +736,8 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
     constexpr long FS = Shape<R, N>::FS;
     constexpr int TZT = TTile<R, N>::TZT;
     static_assert(TZT % TZ == 0, "a y-pass chunk lies inside one field tile");
-    using Lay = TPLayout<N, TZ, true>;
+    constexpr int YR1 = YCfg<R, N>::R1_3;
+    using Lay = TPLayout<N, TZ, true, YR1>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
     constexpr int ITEMS = TZ * R2;
     constexpr int PER = (ITEMS + NT - 1) / NT;
@@ -823,7 +828,7 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
                         v[m] = cmk<C>(-q * wr[0][m].y, q * wr[0][m].x);
                     }
                 }
-                tp_phase1_item<C, N, +1, TZ, true>(v, line, t, lds, twl);
+                tp_phase1_item<C, N, +1, TZ, true, YR1>(v, line, t, lds, twl);
             }
         } else {
             auto ld = [&](int zz, int t, int m) -> C {
@@ -840,12 +845,12 @@ __global__ __launch_bounds__(256) void k_ypass3(const typename CplxOf<R>::T* __r
                 }
                 return v;
             };
-            tp_phase1_tm<C, N, +1, TZ, NT, true>(ld, lds, twl, tid);
+            tp_phase1_tm<C, N, +1, TZ, NT, true, YR1>(ld, lds, twl, tid);
         }
         __syncthreads();
         C* dst = T + (3 * al + j) * FS;
         auto st = [&](int zz, int y, C v) { dst[t_offset<N, TZT>(kx, y, zc * TZ + zz, hs)] = v; };
-        tp_phase2<C, N, +1, TZ, NT, true>(st, lds, tid);
+        tp_phase2<C, N, +1, TZ, NT, true, YR1>(st, lds, tid);
         __syncthreads();
     }
 }
