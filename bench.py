@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on `bench.py --quick`,
 # scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
 # source they were taken on (see the summaries in profiles/).
-COUNTER_SOURCE_SHA = "8cf1284939753a34"
-COUNTER_TRAFFIC = {"xprod": 30841835488.8, "ypass": 48859136434.3, "gen_z": 18802558900.1}
+COUNTER_SOURCE_SHA = "157dc648ea1459dd"
+COUNTER_TRAFFIC = {"xprod": 30865241763.1, "ypass": 48859659506.6, "gen_z": 18802041246.5}
 
 
 def kernel_source_sha() -> str:
