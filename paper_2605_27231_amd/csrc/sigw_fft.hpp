@@ -219,26 +219,37 @@ template <int N, int NL, bool LINE_FAST, int R1_ = 0> struct TPLayout {
     }
 };
 
+// The inter-phase twiddles of phase 1 as an R1 x R2 matrix in LDS:
+// twm[k1 R2 + t] = exp(-2 pi i t k1 / N).  Lanes of one phase-1 pass hold
+// consecutive t, so they read consecutive entries (no bank conflicts, unlike
+// the strided entries t k1 of the plain table).
+template <typename C, int N, int R1, int NT>
+__device__ __forceinline__ void stage_twiddle_matrix(C* twm, const C* __restrict__ tw, int tid) {
+    constexpr int R2 = N / R1;
+    for (int i = tid; i < N; i += NT) twm[i] = tw[((i % R2) * (i / R2)) % N];
+}
+
 // Phase 1 of one item whose inputs are already in registers: a[m] holds
 // element t + R2 m of line `line`; a is overwritten.  The inter-phase
 // twiddles tw[t k1] depend on the lane: with tw a copy of the table in LDS
-// they stay off the vector memory path.
-template <typename C, int N, int SIGN, int NL, bool LINE_FAST, int R1_ = 0>
+// they stay off the vector memory path.  TWM: tw is the twiddle matrix of
+// stage_twiddle_matrix instead of the plain table.
+template <typename C, int N, int SIGN, int NL, bool LINE_FAST, int R1_ = 0, bool TWM = false>
 __device__ __forceinline__ void tp_phase1_item(C* a, int line, int t, C* lds, const C* tw) {
     using Lay = TPLayout<N, NL, LINE_FAST, R1_>;
-    constexpr int R1 = Lay::R1;
+    constexpr int R1 = Lay::R1, R2 = Lay::R2;
     reg_dft<R1, SIGN>(a);
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
         C v = a[k1];
-        if (k1 > 0) v = cmul(v, tw_at<SIGN, N>(tw, t * k1));
+        if (k1 > 0) v = cmul(v, TWM ? tw_at<SIGN, N>(tw, k1 * R2 + t) : tw_at<SIGN, N>(tw, t * k1));
         lds[Lay::at(line, k1, t)] = v;
     }
 }
 
 // Phase 1 over all NL lines, items spread over NT threads; ld(line, n)
 // returns element n of a line.
-template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, class LD>
+template <typename C, int N, int SIGN, int NL, int NT, bool LINE_FAST, bool TWM = false, class LD>
 __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* tw, int tid) {
     using Lay = TPLayout<N, NL, LINE_FAST>;
     constexpr int R1 = Lay::R1, R2 = Lay::R2;
@@ -252,7 +263,7 @@ __device__ __forceinline__ void tp_phase1(LD&& ld, C* lds, const C* tw, int tid)
             C a[R1];
 #pragma unroll
             for (int m = 0; m < R1; ++m) a[m] = ld(line, t + R2 * m);
-            tp_phase1_item<C, N, SIGN, NL, LINE_FAST>(a, line, t, lds, tw);
+            tp_phase1_item<C, N, SIGN, NL, LINE_FAST, 0, TWM>(a, line, t, lds, tw);
         }
     }
 }

@@ -923,7 +923,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
     __shared__ C Z[TRS];                                         // transpose, then G lines
     __shared__ C twl[N];
     const int tid = threadIdx.x;
-    stage_twiddles<C, N, NT>(twl, tw, tid);
+    stage_twiddle_matrix<C, N, TPConst<N>::R1, NT>(twl, tw, tid);   // phase-1 twiddles by (k1, t)
     const int bl = xcd_block(int(blockIdx.x), int(gridDim.x));
     const int zc = bl % NZC;
     const int y = bl / NZC;
@@ -1024,7 +1024,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
                     C o = v[k1];
-                    if (k1 > 0) o = cmul(o, tw_at<+1, N>(twl, t * k1));
+                    if (k1 > 0) o = cmul(o, tw_at<+1, N>(twl, k1 * R2 + t));
                     Z[LayI::at(j * P + p, k1, t)] = o;
                 }
             }
@@ -1078,7 +1078,7 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
             zq[(qq / N) * LS + (qq % N)] = Q[c][i];
         }
         __syncthreads();
-        tp_phase1<C, N, -1, P, NT, false>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, twl, tid);
+        tp_phase1<C, N, -1, P, NT, false, true>([&](int p, int x) -> C { return zq[p * LS + x]; }, zt, twl, tid);
         __syncthreads();
         TPRegs<C, N, -1, P, NT, false> f;
         f.run(zt, tid);
