@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on `bench.py --quick`,
 # scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
 # source they were taken on (see the summaries in profiles/).
-COUNTER_SOURCE_SHA = "157dc648ea1459dd"
-COUNTER_TRAFFIC = {"xprod": 30865241763.1, "ypass": 48859659506.6, "gen_z": 18802041246.5}
+COUNTER_SOURCE_SHA = "2b50ff3aa49d9722"
+COUNTER_TRAFFIC = {"xprod": 30949007162.5, "ypass": 48859741577.8, "gen_z": 18802134179.3}
 
 
 def kernel_source_sha() -> str:
