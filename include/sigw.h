@@ -134,6 +134,22 @@ sigw_status sigw_plan_destroy(sigw_plan_t plan);
 sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma, double* phi,
                               double* edges);
 
+/* Replace kernel m's separable table in a plan with the caller's own, in the
+ * layout sigw_kernel_table returns: sigma[n_alpha], phi[n_modes * n_alpha]
+ * (phi_a on interval i at phi[i * n_alpha + a]) and, unless NULL, the u grid
+ * edges[n_modes + 1], which both kernels share (a new grid replaces it for
+ * m = 0 and 1 alike, so set both tables on it).  n_modes and n_alpha are
+ * the plan's.  The sum_a sigma_a phi_a(u) phi_a(v) then stands for the
+ * kernel I_m(u, v) of Eq. decomposition whatever it was built from: tables
+ * for other equations of state or thermal histories, other grids or bases
+ * (the device path reads only the table).  phi_a is zero outside
+ * [edges[0], edges[n_modes]).  Host arrays, read during the call; waits for
+ * the plan's enqueued work, then copies.  SIGW_E_INVALID for m not in
+ * {0, 1}, NULL sigma or phi, non-finite values, or edges not strictly
+ * increasing from a value >= 0; the plan is then unchanged. */
+sigw_status sigw_plan_set_kernel_table(sigw_plan_t plan, int32_t m, const double* sigma, const double* phi,
+                                       const double* edges);
+
 /* White noise of one seed: one N(0,1) deviate per site (Philox4x64-10 with
  * key (seed, 0) and counter (site, 0, 0, 0), site = (x N + y) N + z; the
  * Box-Muller cosine branch with the binary64 ln/cos sequence documented in

@@ -56,13 +56,16 @@ def grid_edges(n_modes, u_min, u_max, u_p, sigma_p, A_p) -> np.ndarray:
     return e
 
 
-def kernel_matrix(edges: np.ndarray, which: str) -> np.ndarray:
-    """C_ij = sqrt(L_i L_j) I(c_i, c_j) inside the triangle strip, else 0."""
+def kernel_matrix(edges: np.ndarray, which: str, kernel=None) -> np.ndarray:
+    """C_ij = sqrt(L_i L_j) I(c_i, c_j) inside the triangle strip, else 0.
+    I is I_s or I_c of Eq. kernels, or the callable kernel(u, v) if given
+    (another kernel on the same strip, e.g. from another equation of
+    state)."""
     c = 0.5 * (edges[:-1] + edges[1:])
     L = edges[1:] - edges[:-1]
     U, Vv = np.meshgrid(c, c, indexing="ij")
     strip = (np.abs(U - Vv) <= 1.0) & (U + Vv >= 1.0)
-    f = kernels.I_s if which == "s" else kernels.I_c
+    f = kernel if kernel is not None else (kernels.I_s if which == "s" else kernels.I_c)
     with np.errstate(all="ignore"):
         K = np.where(strip, f(U, Vv), 0.0)
     return np.sqrt(np.outer(L, L)) * K
@@ -92,9 +95,9 @@ class KernelTable:
 
 
 def decompose(which: str, n_modes=200, n_alpha=50, u_min=1e-3, u_max=15.0,
-              u_p=1.0, sigma_p=0.5, A_p=10.0) -> KernelTable:
+              u_p=1.0, sigma_p=0.5, A_p=10.0, kernel=None) -> KernelTable:
     edges = grid_edges(n_modes, u_min, u_max, u_p, sigma_p, A_p)
-    C = kernel_matrix(edges, which)
+    C = kernel_matrix(edges, which, kernel)
     w, Q = np.linalg.eigh(C)
     order = np.argsort(-np.abs(w), kind="stable")
     w = w[order]

@@ -33,7 +33,7 @@ EXPORTS = (
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
     "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
-    "sigw_spectrum_adaptive",
+    "sigw_spectrum_adaptive", "sigw_plan_set_kernel_table",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -111,6 +111,7 @@ def lib() -> ct.CDLL:
                                    ct.c_int32, D, ct.c_double, D, I64, D],
         "sigw_plan_schedule": [P, I32, I32, ct.c_char_p, ct.c_size_t],
         "sigw_plan_set_schedule": [P, ct.c_int32],
+        "sigw_plan_set_kernel_table": [P, ct.c_int32, D, D, D],
     }
     for name, args in sig.items():
         f = getattr(L, name)

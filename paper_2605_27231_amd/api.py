@@ -230,6 +230,22 @@ class Plan:
     def graph(self, slots: Sequence[int], targets, k_lo, k_hi) -> "SpectrumGraph":
         return SpectrumGraph(self, slots, targets, k_lo, k_hi)
 
+    # -- kernel tables --------------------------------------------------------
+    def set_kernel_table(self, m: int, sigma, phi, edges=None):
+        """Use the caller's separable table for kernel m (0 = I_s, 1 = I_c):
+        sigma[n_alpha], phi[n_modes, n_alpha], and optionally a new u grid
+        edges[n_modes + 1] shared by both kernels."""
+        s = np.ascontiguousarray(sigma, dtype=np.float64)
+        f = np.ascontiguousarray(phi, dtype=np.float64)
+        e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float64)
+        d = self.desc
+        if s.shape != (d.n_alpha,) or f.shape != (d.n_modes, d.n_alpha) or (
+                e is not None and e.shape != (d.n_modes + 1,)):
+            raise ValueError("table shapes must be sigma[n_alpha], phi[n_modes, n_alpha], edges[n_modes + 1]")
+        self._chk(lib().sigw_plan_set_kernel_table(self.h, int(m), _dptr(s), _dptr(f),
+                                                   None if e is None else _dptr(e)),
+                  "sigw_plan_set_kernel_table")
+
     # -- x-pass schedule ------------------------------------------------------
     def autotune(self, force: bool = False) -> str:
         self._chk(lib().sigw_autotune(self.h, _lib.SIGW_TUNE_FORCE if force else 0), "sigw_autotune")

@@ -765,6 +765,46 @@ sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma,
     return SIGW_OK;
 }
 
+sigw_status sigw_plan_set_kernel_table(sigw_plan_t p, int32_t m, const double* sigma, const double* phi,
+                                       const double* edges) {
+    if (!p) return SIGW_E_INVALID;
+    if ((m != 0 && m != 1) || !sigma || !phi) return fail(p, SIGW_E_INVALID, "need m in {0, 1}, sigma and phi");
+    const sigw_plan_desc& d = p->d;
+    const size_t na = size_t(d.n_alpha), nm = size_t(d.n_modes);
+    for (size_t i = 0; i < na; ++i)
+        if (!std::isfinite(sigma[i])) return fail(p, SIGW_E_INVALID, "sigma must be finite");
+    for (size_t i = 0; i < nm * na; ++i)
+        if (!std::isfinite(phi[i])) return fail(p, SIGW_E_INVALID, "phi must be finite");
+    if (edges) {
+        if (!std::isfinite(edges[0]) || !(edges[0] >= 0.0))
+            return fail(p, SIGW_E_INVALID, "edges must start at a finite u >= 0");
+        for (size_t i = 1; i <= nm; ++i)
+            if (!std::isfinite(edges[i]) || !(edges[i] > edges[i - 1]))
+                return fail(p, SIGW_E_INVALID, "edges must be finite and strictly increasing");
+    }
+    const Sizes& z = p->z;
+    std::vector<char> sh(na * z.rb), ph(nm * na * z.rb);
+    for (size_t i = 0; i < na; ++i) {
+        if (d.prec == SIGW_F64) reinterpret_cast<double*>(sh.data())[i] = sigma[i];
+        else reinterpret_cast<float*>(sh.data())[i] = float(sigma[i]);
+    }
+    for (size_t i = 0; i < nm * na; ++i) {
+        if (d.prec == SIGW_F64) reinterpret_cast<double*>(ph.data())[i] = phi[i];
+        else reinterpret_cast<float*>(ph.data())[i] = float(phi[i]);
+    }
+    // work already enqueued reads the tables: let it finish first
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    HIP_TRY(p, hipMemcpy(p->sigma_tab[m], sh.data(), sh.size(), hipMemcpyHostToDevice));
+    HIP_TRY(p, hipMemcpy(p->phi_tab[m], ph.data(), ph.size(), hipMemcpyHostToDevice));
+    p->tab_h[m].sigma.assign(sigma, sigma + na);
+    p->tab_h[m].phi.assign(phi, phi + nm * na);
+    if (edges) {
+        HIP_TRY(p, hipMemcpy(p->edges, edges, (nm + 1) * 8, hipMemcpyHostToDevice));
+        p->edges_h.assign(edges, edges + nm + 1);     // the support bound follows the new grid
+    }
+    return SIGW_OK;
+}
+
 sigw_status sigw_plan_destroy(sigw_plan_t p) {
     if (!p) return SIGW_E_INVALID;
     (void)hipStreamSynchronize(p->stream);
