@@ -144,7 +144,10 @@ sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma,
  * for other equations of state or thermal histories, other grids or bases
  * (the device path reads only the table).  phi_a is zero outside
  * [edges[0], edges[n_modes]).  Host arrays, read during the call; waits for
- * the plan's enqueued work, then copies.  SIGW_E_INVALID for m not in
+ * the plan's enqueued work, then copies.  Spectrum graphs of the plan
+ * (sigw_graph_create) read the new tables when launched but keep the
+ * support bounds and grids chosen from the grid they were created with:
+ * create them again after a new grid.  SIGW_E_INVALID for m not in
  * {0, 1}, NULL sigma or phi, non-finite values, or edges not strictly
  * increasing from a value >= 0; the plan is then unchanged. */
 sigw_status sigw_plan_set_kernel_table(sigw_plan_t plan, int32_t m, const double* sigma, const double* phi,
