@@ -73,6 +73,15 @@ FIXTURES = {
     "exptail512_fp64_oracle": lambda: sampled(
         W.config_exptail(512, 96), [(0, [44, 66, 80])], "exptail512_fp64_oracle",
         "512^3 exp-tail beta=3 clip 1e-6, A=5e-3, sigma=0.3, k*=40, 96 log bins; FP64 oracle"),
+    # the same two workloads at targets that the hot path computes on smaller
+    # grids of the same box (32^3, 64^3, 128^3 for the 256^3 lattice; 256^3
+    # and 384^3 for the 512^3 one)
+    "local256_small_fp64_oracle": lambda: sampled(
+        W.config_local_ng(256, 64), [(0, [0, 7, 14])], "local256_small_fp64_oracle",
+        "256^3 local NG f_NL=5 (F_NL=3), A=1e-2, sigma=0.5, k*=20, 64 log bins, bins 0/7/14; FP64 oracle"),
+    "exptail512_small_fp64_oracle": lambda: sampled(
+        W.config_exptail(512, 96), [(0, [28, 40])], "exptail512_small_fp64_oracle",
+        "512^3 exp-tail beta=3 clip 1e-6, A=5e-3, sigma=0.3, k*=40, 96 log bins, bins 28/40; FP64 oracle"),
     # the first four realisations of the 128^3 ensemble (parameters drawn per realisation), 32 log bins
     "ensemble128_fp64_oracle": lambda: ensemble_sampled(
         W.config_ensemble(128, 4, 32), [10, 18, 24], "ensemble128_fp64_oracle",
