@@ -7,9 +7,10 @@ tests/golden/make_golden.py, which calls only the oracle):
 * 512^3 exponential tail (beta = 3, clip 1e-6, A = 5e-3, sigma = 0.3,
   k* = 40, 96 log bins), seed 0, low tail / peak / high tail:
   exptail512_fp64_oracle.json;
-* the 256^3 workload at bins that the path computes on smaller grids of
-  the same box (bins 0, 7, 14 on 32^3, 64^3, 128^3):
-  local256_small_fp64_oracle.json.
+* the same two workloads at bins that the path computes on smaller grids
+  of the same box (256^3: bins 0, 7, 14 on 32^3, 64^3, 128^3; 512^3: bins
+  28, 40 on 256^3, 384^3): local256_small_fp64_oracle.json,
+  exptail512_small_fp64_oracle.json.
 
 Bars: FP32 path within 1e-4 relative per sampled bin; FP64 path within
 1e-10; mode counts exact.
@@ -46,6 +47,7 @@ CASES = {
     "local256_fp64_oracle": lambda: W.config_local_ng(256, 64),
     "exptail512_fp64_oracle": lambda: W.config_exptail(512, 96),
     "local256_small_fp64_oracle": lambda: W.config_local_ng(256, 64),
+    "exptail512_small_fp64_oracle": lambda: W.config_exptail(512, 96),
 }
 
 
