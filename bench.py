@@ -1,6 +1,6 @@
 """Benchmark of the lattice Omega_GW path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
                     [--workload local256|exptail512]
 
 Default workload (local256): one step = the whole hot path for one batch:
@@ -12,13 +12,17 @@ cost nothing).  exptail512: eight realisations (seeds 0..7) of a 512^3
 exponential-tail field (beta = 3, clip 1e-6; A = 5e-3, sigma = 0.3, k* = 40)
 in 96 log bins, averaged over the seeds.  Fields and FFTs are FP32
 (complex64); maps, lookup tables and shell sums are FP64.  Inputs (plans,
-tables) are resident before the timed region.  --fp64 adds the FP64 path on
-seed 0: its speed and the per-bin FP32 error against it.
+tables) are resident before the timed region.  After the timed region the
+FP64 path runs seed 0 (skip with --no-fp64): its speed, the FP32 speedup over
+it, and the per-bin FP32 error against it.
 
 Prints one JSON line with the throughput in spectra/s (one spectrum = one
 realisation x all its bins), the roofline of the dominant kernel measured
-live with HIP events on the plan stream, and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+live with HIP events on the plan stream plus the end-to-end fraction of the
+two-pass byte model, the timed step's per-bin error against the FP64 oracle
+values stored in tests/golden/ (exit status 1 above 1e-4, or above 1e-10
+for the FP64 path), and the FP64 oracle timed on the host cores on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -65,14 +69,26 @@ def stage_terms(N: int, cb: int, n_alpha: int = 50) -> int:
     return max(1, min(n_alpha, (16 << 30) // (2 * FS * cb)))
 
 
+def lattice_n2(N: int) -> np.ndarray:
+    """Which |n|^2 in [0, 3 (N/2)^2] some mode of the N^3 lattice has (|n_c| <= N/2)."""
+    h = N // 2
+    sq = np.arange(h + 1) ** 2
+    two = np.zeros(2 * h * h + 1, bool)
+    two[(sq[:, None] + sq[None, :]).ravel()] = True
+    three = np.zeros(3 * h * h + 1, bool)
+    s2 = np.nonzero(two)[0]
+    three[(s2[:, None] + sq[None, :]).ravel()] = True
+    return three
+
+
 def shell_n2_hi(N: int, L: float, k_lo: float, k_hi: float):
-    """Largest integer |n|^2 of the shell k_lo <= k_F |n| < k_hi (None when
-    the shell holds no lattice mode); the planes kx <= sqrt of it carry the
-    shell."""
+    """Largest |n|^2 of a lattice mode in the shell k_lo <= k_F |n| < k_hi
+    (None when the shell holds no lattice mode; such a target launches
+    nothing); the planes kx <= sqrt of it carry the shell."""
     kF = 2 * math.pi / L
     n2 = np.arange(3 * (N // 2) ** 2 + 1)
     k = kF * np.sqrt(n2)
-    sel = n2[(n2 > 0) & (k >= k_lo) & (k < k_hi)]
+    sel = n2[(n2 > 0) & (k >= k_lo) & (k < k_hi) & lattice_n2(N)]
     return int(sel[-1]) if len(sel) else None
 
 
@@ -144,6 +160,74 @@ def algorithmic_bytes(N: int, L: float, cb: int, n_alpha: int, u_max: float, tar
     return {k: (tot[k] / cnt[k] if cnt[k] else 0.0) for k in tot}
 
 
+def p2_model_bytes(N: int, L: float, cb: int, n_alpha: int, u_max: float, targets, k_lo, k_hi):
+    """Bytes per realisation of one spectrum under the two-pass-per-3D-FFT
+    model (p = 2: one intermediate HBM round trip per transform; the first
+    inverse pass and the last forward pass fused with the weighting and the
+    shell sums): per target and kernel m, Phi_hat read once, 3 gradient
+    fields per term written and read once, 6 components of Q written and
+    read once.  Returns (pruned, dense): pruned counts only the support of
+    each target on the grid it runs on (live rows for Phi_hat, planes
+    kx <= kx_sup for the fields, the shell's planes for Q), dense counts the
+    whole N^3 lattice for every target that holds modes (626 half spectra
+    per target at n_alpha = 50)."""
+    H_N = N // 2 + 1
+    S_N = H_N * N * N * cb
+    pruned = dense = 0.0
+    for kt, lo, hi in zip(targets, k_lo, k_hi):
+        n2_hi = shell_n2_hi(N, L, lo, hi)
+        if n2_hi is None:
+            continue
+        M = target_grid(N, L, kt, u_max, n2_hi)
+        H = M // 2 + 1
+        plane = M * M
+        n2s = min(support_n2(N, L, kt, u_max), 3 * (M // 2) ** 2)
+        kxs = min(H - 1, math.isqrt(n2s))
+        n_planes = min(H - 1, math.isqrt(n2_hi)) + 1
+        ny2 = np.fft.fftfreq(M, 1.0 / M) ** 2
+        kx2 = np.arange(kxs + 1)[:, None] ** 2
+        rows = int(((kx2 + ny2[None, :]) <= n2s).sum())
+        pruned += 2 * (rows * M + 6 * n_alpha * (kxs + 1) * plane + 12 * n_planes * plane) * cb
+        dense += 2 * (1 + 6 * n_alpha + 12) * S_N
+    return pruned, dense
+
+
+def load_goldens(workload: str):
+    """Stored FP64 oracle values of this workload (tests/golden/*.json,
+    written by tests/golden/make_golden.py from the oracle alone):
+    {(seed, bin): (omega, nmodes)}."""
+    import glob
+    out = {}
+    prefix = {"local256": "local256", "exptail512": "exptail512"}[workload]
+    for path in sorted(glob.glob(os.path.join(ROOT, "tests", "golden", prefix + "*_fp64_oracle.json"))):
+        with open(path) as f:
+            g = json.load(f)
+        for smp in g["samples"]:
+            out[(int(smp["seed"]), int(smp["bin"]))] = (float(smp["omega"]), int(smp["nmodes"]))
+    return out
+
+
+def parity_check(per_seed: dict, goldens: dict, tol: float):
+    """Per-bin relative error of the timed step's spectra against the stored
+    oracle values (every stored bin of every seed the step computed), and
+    whether the mode counts are equal."""
+    errs, bins, counts_ok = [], [], True
+    for (seed, b), (om_ref, nb_ref) in sorted(goldens.items()):
+        if seed not in per_seed:
+            continue
+        om, nb = per_seed[seed]
+        if int(nb[b]) != nb_ref:
+            counts_ok = False
+        errs.append(abs(float(om[b]) - om_ref) / abs(om_ref))
+        bins.append([seed, b])
+    if not errs:
+        return {"max_rel_err": None, "bins": 0, "tol": tol, "ok": True}
+    return {"max_rel_err": float(max(errs)), "median_rel_err": float(np.median(errs)), "bins": len(errs),
+            "seeds": sorted({s for s, _ in bins}), "nmodes_equal": counts_ok, "tol": tol,
+            "ok": bool(max(errs) <= tol and counts_ok),
+            "against": "FP64 oracle values stored in tests/golden/ (seed, bin) of this workload"}
+
+
 def kernel_u_max(N: int, prec: str = "f32") -> float:
     """Last edge of the kernel table's u grid (the support of every phi_a)."""
     import paper_2605_27231_amd as P
@@ -198,7 +282,7 @@ def run_gpu(args):
             dt = time.perf_counter() - t0
             for j, i in enumerate(grp):
                 lat.append(dt)
-                per_seed[seeds[i]] = om_b[j]
+                per_seed[seeds[i]] = (om_b[j], nb_b[j])
             if job.N > 256:
                 say(f"seeds {[seeds[i] for i in grp]}: {dt:.2f} s")
         return om_b[-1], nb_b[-1]
@@ -240,6 +324,24 @@ def run_gpu(args):
         ms, n = times[k]
         kernels[k] = {"avg_ms": round(ms, 4), "launches": n}
     lat_ms = np.array(lat) * 1e3
+    # end to end: the p = 2 model's bytes of every realisation and target of
+    # a step over the measured time per step, and the bytes the kernels of
+    # this design actually have to move (their algorithmic bytes x launches)
+    p2_pruned, p2_dense = p2_model_bytes(job.N, job.L, cb, 50, u_max, job.targets, job.k_lo, job.k_hi)
+    t_step = dt / args.steps
+    moved = sum(ab[k] * times[k][1] for k in ("gen_z", "ypass", "xprod")) / args.steps
+    e2e = {"p2_bytes_per_step": round(p2_pruned * len(seeds)),
+           "p2_frac": round(p2_pruned * len(seeds) / t_step / 1e9 / HBM_PEAK_GBS, 4),
+           "p2_dense_bytes_per_step": round(p2_dense * len(seeds)),
+           "p2_dense_frac": round(p2_dense * len(seeds) / t_step / 1e9 / HBM_PEAK_GBS, 4),
+           "design_bytes_per_step": round(moved),
+           "design_GB_s": round(moved / t_step / 1e9, 1),
+           "design_frac": round(moved / t_step / 1e9 / HBM_PEAK_GBS, 4),
+           "what": "p2: bytes of the two-pass-per-3D-FFT model (Phi_hat once, 3 fields per term and 6 "
+                   "components of Q each written and read once, per target and kernel) on each target's "
+                   "support and grid (p2) or the whole lattice (p2_dense), over the time per step; design: "
+                   "algorithmic bytes of this build's three hot kernels (10 half spectra per term) over the "
+                   "time per step"}
     res = {
         "value": value, "dt": dt, "n_targets": n_targets, "omega_seed_last": om.tolist(),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -248,19 +350,21 @@ def run_gpu(args):
                                  else None),
                      "kernel": dom,
                      "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(ms_d, 4),
-                     "launches": n_d},
+                     "launches": n_d, "end_to_end": e2e},
         "kernels": kernels,
         "schedule": schedule,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "what": f"one spectrum (field generation + {len(job.targets)} bins) end to end; "
                                f"the {batch} spectra of a batch complete together"},
         "batch": batch,
-        "omega_seed_mean": np.mean([per_seed[s] for s in seeds], axis=0).tolist(),
+        "omega_seed_mean": np.mean([per_seed[s][0] for s in seeds], axis=0).tolist(),
         "targets": job.targets.tolist(),
         "nmodes": nb.tolist(),
     }
     plan.close()
-    if args.fp64:
+    goldens = load_goldens(args.workload)
+    res["parity"] = parity_check(per_seed, goldens, 1e-4)
+    if not args.no_fp64:
         pl64 = P.Plan(job.N, L=job.L, prec="f64", n_slots=1, autotune=1)
         say("FP64 path: warm-up spectrum of seed 0")
         pl64.generate_field(0, seeds[0], job.spectrum, job.ngmap)
@@ -273,15 +377,17 @@ def run_gpu(args):
         d64 = time.perf_counter() - t1
         pl64.close()
         say(f"FP64 path: {d64:.2f} s per spectrum")
-        om32 = per_seed[seeds[0]]
+        om32 = per_seed[seeds[0]][0]
         ok = nb64 > 0
         rel = np.zeros_like(om64)
         rel[ok] = np.abs(om32[ok] - om64[ok]) / np.abs(om64[ok])
         res["fp64_path"] = {"spectra_per_s": 1.0 / d64, "speedup_fp32_over_fp64": value * d64,
                             "fp32_rel_err_per_bin": {"max": float(rel.max()), "median": float(np.median(rel[ok])),
                                                      "bins": [float(x) for x in rel]},
-                            "nmodes_equal": bool(np.array_equal(nb64, nb)),
-                            "what": f"seed {seeds[0]} only, same bins, FP64 fields/FFTs"}
+                            "nmodes_equal": bool(np.array_equal(nb64, per_seed[seeds[0]][1])),
+                            "parity": parity_check({seeds[0]: (om64, nb64)}, goldens, 1e-10),
+                            "what": f"seed {seeds[0]} only, same bins, FP64 fields/FFTs; one spectrum "
+                                    f"timed after a warm-up spectrum, field generation included"}
     return res
 
 
@@ -354,7 +460,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64", action="store_true", help="also time the FP64 path on one seed")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path (timed on one seed by default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true",
                     help="one field + one target + a 1 GiB copy, for hardware-counter passes")
@@ -399,6 +505,7 @@ def main():
         "latency_ms": g["latency_ms"],
         "cpu_baseline": cpu,
     }
+    line["parity"] = g["parity"]
     if "fp64_path" in g:
         line["fp64_path"] = g["fp64_path"]
     if args.workload != "local256":
@@ -406,6 +513,12 @@ def main():
         line["targets"] = g["targets"]
         line["nmodes"] = g["nmodes"]
     print(json.dumps(line), flush=True)
+    # the timed spectra must match the stored oracle values (and the FP64
+    # path its own bar): otherwise the throughput above is not a result
+    bad = not g["parity"]["ok"] or ("fp64_path" in g and not g["fp64_path"]["parity"]["ok"])
+    if bad:
+        print("[bench] PARITY FAILURE against the stored oracle values", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -145,9 +145,9 @@ sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma,
  * (the device path reads only the table).  phi_a is zero outside
  * [edges[0], edges[n_modes]).  Host arrays, read during the call; waits for
  * the plan's enqueued work, then copies.  Spectrum graphs of the plan
- * (sigw_graph_create) read the new tables when launched but keep the
- * support bounds and grids chosen from the grid they were created with:
- * create them again after a new grid.  SIGW_E_INVALID for m not in
+ * (sigw_graph_create) read the new tables when launched; a graph captured
+ * before a new u grid was set keeps the support bounds and grids of the old
+ * one, so sigw_graph_launch refuses it with SIGW_E_STATE: create it again.  SIGW_E_INVALID for m not in
  * {0, 1}, NULL sigma or phi, non-finite values, or edges not strictly
  * increasing from a value >= 0; the plan is then unchanged. */
 sigw_status sigw_plan_set_kernel_table(sigw_plan_t plan, int32_t m, const double* sigma, const double* phi,
@@ -168,7 +168,10 @@ sigw_status sigw_generate_field(sigw_plan_t plan, int32_t slot, uint64_t seed,
                                 const sigw_lognormal* spectrum, const sigw_ngmap* ngmap);
 
 /* Use a caller's own real curvature field zeta (device, real layout, path
- * precision) for a slot: Phi_hat = dV DFT(2 zeta / 3).  Enqueues only. */
+ * precision) for a slot: the method takes a given realisation of zeta as its
+ * input (Sec. I; Sec. IV computes A and B from it), and the source enters
+ * through Phi = 2 zeta / 3 (Sec. II, radiation domination, w = 1/3), so the
+ * slot gets Phi_hat = dV DFT(2 zeta / 3).  Enqueues only. */
 sigw_status sigw_set_zeta(sigw_plan_t plan, int32_t slot, const void* zeta_dev);
 
 /* Copy a half spectrum Phi_hat into / out of a slot (device, half layout). */
@@ -191,7 +194,10 @@ sigw_status sigw_source_convolutions(sigw_plan_t plan, int32_t slot, double k_ta
  *   S_b = sum_{n in shell} sum_{m} sum_lambda |e^lambda : X^(m)(n)|^2,
  *   X^(s) = -(4/k_b^2) Q_hat^(s),  X^(c) = +(4/k_b^2) Q_hat^(c),
  *   Omega_b = k_b^3 S_b / (48 pi^2 V N_b),  N_b = number of modes in the shell.
- * Shells with no mode give Omega_b = 0, N_b = 0 and cost nothing.
+ * Shells with no lattice mode (including shells whose |n|^2 values no
+ * mode of the N^3 lattice has, e.g. |n|^2 = 7) give Omega_b = 0, N_b = 0
+ * and launch no kernel.  k_lo may be negative (the shell then starts at
+ * n = 0, which is excluded) and k_hi arbitrarily large.
  * A target whose weighted fields (|n_c| <= Rc, phi_a vanishing for
  * u >= u_max) and shell (|n_c| <= Kc) satisfy 2 Rc + Kc < M and 2 Kc + 1 < M
  * for a compiled size M < N is computed on that smaller grid of the same box,
@@ -260,7 +266,7 @@ typedef struct sigw_graph* sigw_graph_t;
 sigw_status sigw_graph_create(sigw_plan_t plan, int32_t n_sel, const int32_t* slots, int32_t n_k,
                               const double* k_targets, const double* k_lo, const double* k_hi,
                               sigw_graph_t* out);
-sigw_status sigw_graph_launch(sigw_graph_t graph);
+sigw_status sigw_graph_launch(sigw_graph_t graph);   /* SIGW_E_STATE if the plan's u grid changed since capture */
 sigw_status sigw_graph_results(sigw_graph_t graph, double* omega_host, int64_t* nmodes_host);
 sigw_status sigw_graph_destroy(sigw_graph_t graph);
 

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import math
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -103,10 +104,13 @@ class Plan:
                                     ct.byref(h))
         check(st, None, f"sigw_plan_create(N={N}, prec={prec})")
         self.h = h
+        self._graphs = weakref.WeakSet()     # live graphs: destroyed before the plan
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
+            for g in list(getattr(self, "_graphs", ())):
+                g.close()
             lib().sigw_plan_destroy(self.h)
             self.h = None
 
@@ -293,6 +297,7 @@ class SpectrumGraph:
                                      ct.byref(h))
         check(st, plan.h, "sigw_graph_create")
         self.h = h
+        plan._graphs.add(self)
 
     def launch(self):
         check(lib().sigw_graph_launch(self.h), self.plan.h, "sigw_graph_launch")

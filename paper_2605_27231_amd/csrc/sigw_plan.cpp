@@ -292,6 +292,8 @@ struct sigw_plan {
     std::string schedule;       // report of the active x-pass schedule
     std::vector<double> edges_h;
     Table tab_h[2];
+    std::vector<uint8_t> lattice_n2;   // |n|^2 values that some lattice mode has
+    int grid_gen = 0;                  // bumped whenever the u grid (edges_h) changes
     // device buffers
     void* tw = nullptr;
     double* edges = nullptr;
@@ -386,15 +388,18 @@ sigw_status collect_times(sigw_plan* p) {
 }
 
 // Integer |n|^2 range of the shell k_lo <= k_F sqrt(n2) < k_hi, n2 > 0, using
-// the same FP64 expression as the device lookup table.
+// the same FP64 expression as the device lookup table.  The scan starts just
+// below max(k_lo, 0)^2 and ends just above k_hi^2, both capped at n2max
+// (which also keeps the casts of huge edges in range).
 bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n2_hi) {
     auto inside = [&](long n2) {
         const double k = kF * std::sqrt((double)n2);
         return n2 > 0 && k >= lo && k < hi;
     };
     if (!(hi > lo)) return false;
-    double a = lo / kF;
-    long start = std::max(1L, (long)std::floor(a * a) - 2);
+    const double a = std::max(lo, 0.0) / kF;
+    const double a2 = a * a;
+    const long start = a2 >= double(n2max) ? n2max : std::max(1L, (long)std::floor(a2) - 2);
     long first = -1;
     for (long n2 = start; n2 <= n2max; ++n2) {
         const double k = kF * std::sqrt((double)n2);
@@ -405,13 +410,46 @@ bool shell_range(double kF, double lo, double hi, long n2max, int* n2_lo, int* n
         }
     }
     if (first < 0) return false;
-    double b = hi / kF;
-    long last = std::min(n2max, (long)std::ceil(b * b) + 2);
+    const double b = hi / kF;
+    const double b2 = b * b;
+    long last = b2 >= double(n2max) ? n2max : std::min(n2max, (long)std::ceil(b2) + 2);
     while (last >= first && !inside(last)) --last;
     if (last < first) return false;
     // every integer in [first, last] satisfies the monotone predicate
     *n2_lo = int(first);
     *n2_hi = int(last);
+    return true;
+}
+
+// Which |n|^2 in [0, 3 (N/2)^2] some mode of the N^3 lattice has: sums
+// nx^2 + ny^2 + nz^2 with |n_c| <= N/2 (the signed index -N/2 has |n_c| =
+// N/2).  Not every integer is one (none of the form 4^a (8b + 7), and near
+// the corner of the cube fewer still), so a shell can hold |n|^2 values and
+// still no mode.
+std::vector<uint8_t> lattice_n2_table(int N) {
+    const int h = N / 2;
+    const long n2max = 3L * h * h;
+    std::vector<uint8_t> two(size_t(2L * h * h + 1), 0), three(size_t(n2max + 1), 0);
+    for (int x = 0; x <= h; ++x)
+        for (int y = 0; y <= x; ++y) two[size_t(x * x + y * y)] = 1;
+    for (long s = 0; s <= 2L * h * h; ++s)
+        if (two[size_t(s)])
+            for (int z = 0; z <= h; ++z) three[size_t(s + long(z) * z)] = 1;
+    return three;
+}
+
+// The |n|^2 range of the modes a shell holds on the plan's lattice: the
+// shell's integer range trimmed to values some lattice mode has.  False when
+// the shell holds no mode; such a target gives N_b = 0 and launches nothing.
+bool shell_modes(const sigw_plan* p, double lo, double hi, int* n2_lo, int* n2_hi) {
+    const double kF = 2.0 * kPi / p->d.L;
+    int a = 0, b = -1;
+    if (!shell_range(kF, lo, hi, p->z.n2max, &a, &b)) return false;
+    while (a <= b && !p->lattice_n2[size_t(a)]) ++a;
+    while (b >= a && !p->lattice_n2[size_t(b)]) --b;
+    if (a > b) return false;
+    *n2_lo = a;
+    *n2_hi = b;
     return true;
 }
 
@@ -565,7 +603,7 @@ sigw_status enqueue_spectrum(sigw_plan* p, const int* sel_dev, int n_sel, int n_
     valid.assign(n_k, 0);
     for (int b = 0; b < n_k; ++b) {
         int n2_lo = 0, n2_hi = -1;
-        if (!shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi)) continue;
+        if (!shell_modes(p, lo[b], hi[b], &n2_lo, &n2_hi)) continue;
         valid[b] = 1;
         // the plan's lattice, or the smallest grid that gives the same sums
         const int ci = own_grid_only ? -1 : coarse_grid_for(p, kt[b], n2_hi);
@@ -801,6 +839,7 @@ sigw_status sigw_plan_set_kernel_table(sigw_plan_t p, int32_t m, const double* s
     if (edges) {
         HIP_TRY(p, hipMemcpy(p->edges, edges, (nm + 1) * 8, hipMemcpyHostToDevice));
         p->edges_h.assign(edges, edges + nm + 1);     // the support bound follows the new grid
+        ++p->grid_gen;                                 // graphs captured on the old grid are stale
     }
     return SIGW_OK;
 }
@@ -842,6 +881,11 @@ sigw_status sigw_plan_create(const sigw_plan_desc* d, void* hip_stream, sigw_pla
     p->z = sizes_of(*d);
     p->stream = static_cast<hipStream_t>(hip_stream);
     p->has_field.assign(d->n_slots, 0);
+    try {
+        p->lattice_n2 = lattice_n2_table(d->N);
+    } catch (const std::bad_alloc&) {
+        return SIGW_E_NOMEM;
+    }
     // Sec. V tables on the host (built once per parameter set in the process)
     try {
         const std::shared_ptr<const Decomposition> dec = decomposition_of(*d);
@@ -1167,7 +1211,7 @@ sigw_status sigw_spectrum_jackknife(sigw_plan_t p, int32_t slot, int32_t n_k, co
         double* S_i = p->part_sum;     // after finalize has consumed the zbin partials
         if (valid[0]) {
             int n2_lo = 0, n2_hi = -1;
-            shell_range(kF, lo[b], hi[b], z.n2max, &n2_lo, &n2_hi);
+            shell_modes(p, lo[b], hi[b], &n2_lo, &n2_hi);
             p->eng->ztt(p->Q, p->lut_shell, n2_lo, n2_hi, p->stream);
             for (int c = 0; c < 12; ++c) {
                 void* comp = cplx_at(p->Q, long(c) * z.FS, z.cb);
@@ -1316,6 +1360,7 @@ struct sigw_graph {
     int n_sel = 0, n_k = 0;
     std::vector<double> kt;
     std::vector<int> valid;
+    int grid_gen = 0;           // the plan's u-grid generation at capture
     int* d_slots = nullptr;
     double* d_sums = nullptr;
     unsigned long long* d_cnts = nullptr;
@@ -1355,6 +1400,7 @@ sigw_status sigw_graph_create(sigw_plan_t p, int32_t n_sel, const int32_t* slots
     std::unique_ptr<sigw_graph> gr(new (std::nothrow) sigw_graph());
     if (!gr) return SIGW_E_NOMEM;
     gr->p = p;
+    gr->grid_gen = p->grid_gen;
     gr->n_sel = n_sel;
     gr->n_k = n_k;
     gr->kt.assign(kt, kt + n_k);
@@ -1409,6 +1455,8 @@ sigw_status sigw_graph_create(sigw_plan_t p, int32_t n_sel, const int32_t* slots
 sigw_status sigw_graph_launch(sigw_graph_t gr) {
     if (!gr) return SIGW_E_INVALID;
     sigw_plan* p = gr->p;
+    if (gr->grid_gen != p->grid_gen)
+        return fail(p, SIGW_E_STATE, "the plan's u grid changed after this graph was captured: create it again");
     HIP_TRY(p, hipGraphLaunch(gr->ge, p->stream));
     gr->launched = true;
     return SIGW_OK;

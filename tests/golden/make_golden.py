@@ -29,6 +29,19 @@ def _job_dict(job):
             "G_NL": job.ngmap.G_NL, "beta": job.ngmap.beta, "clip": job.ngmap.clip}
 
 
+def _write(out, name):
+    tmp = os.path.join(HERE, name + ".json.tmp")
+    with open(tmp, "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(tmp, os.path.join(HERE, name + ".json"))
+
+
+def nonempty_bins(job):
+    """Bins whose shell holds at least one lattice mode (oracle mode count)."""
+    nb = spectrum.mode_counts(job.N, job.L, job.k_lo, job.k_hi)
+    return [int(b) for b in np.nonzero(nb > 0)[0]]
+
+
 def sampled(job, seeds_bins, name, note):
     tabs = decomposition.tables()
     out = {"name": name, "note": note, "job": _job_dict(job), "samples": [],
@@ -43,8 +56,8 @@ def sampled(job, seeds_bins, name, note):
                                    "k_lo": float(job.k_lo[b]), "k_hi": float(job.k_hi[b]),
                                    "omega": float(om), "nmodes": int(nb)})
             print(name, seed, b, om, nb, f"{time.time() - t0:.0f}s", flush=True)
-    with open(os.path.join(HERE, name + ".json"), "w") as f:
-        json.dump(out, f, indent=1)
+            _write(out, name)      # after every sample, so that a long run keeps what it has
+    _write(out, name)
 
 
 def ensemble_sampled(jobs, bins, name, note):
@@ -65,6 +78,20 @@ def ensemble_sampled(jobs, bins, name, note):
 
 
 FIXTURES = {
+    # 256^3 local NG, seed 0 at every bin that holds modes (57 of 64), and
+    # seeds 1..3 at 8 bins each spanning the smaller grids, the rise, the
+    # peak, the tail and the Nyquist corner: the whole spectrum the
+    # benchmark computes, in its batch-of-four launch configuration
+    "local256_seeds123_fp64_oracle": lambda: sampled(
+        W.config_local_ng(256, 64), [(s, [0, 9, 16, 24, 33, 44, 53, 63]) for s in (1, 2, 3)],
+        "local256_seeds123_fp64_oracle",
+        "256^3 local NG f_NL=5 (F_NL=3), A=1e-2, sigma=0.5, k*=20, 64 log bins, seeds 1..3 x 8 bins; "
+        "FP64 oracle"),
+    "local256_seed0_all_fp64_oracle": lambda: sampled(
+        W.config_local_ng(256, 64), [(0, nonempty_bins(W.config_local_ng(256, 64)))],
+        "local256_seed0_all_fp64_oracle",
+        "256^3 local NG f_NL=5 (F_NL=3), A=1e-2, sigma=0.5, k*=20, 64 log bins, seed 0, every "
+        "non-empty bin; FP64 oracle"),
     # 256^3 local NG (f_NL = 5), 64 log bins, seeds 0..3: low tail, rise, peak, high tail
     "local256_fp64_oracle": lambda: sampled(
         W.config_local_ng(256, 64), [(0, [20, 33, 44, 60]), (3, [44])], "local256_fp64_oracle",
