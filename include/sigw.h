@@ -305,7 +305,36 @@ sigw_status sigw_synchronize(sigw_plan_t plan);
 sigw_status sigw_set_timing(sigw_plan_t plan, int32_t enabled);
 sigw_status sigw_kernel_time(sigw_plan_t plan, const char* name, double* avg_ms, int64_t* launches);
 
-const char* sigw_last_error(sigw_plan_t plan);
+/* Allocation-free spectrum, for callers that cannot allocate device memory
+ * (code under HIP graph capture's restrictions, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes what sigw_plan_create +
+ * sigw_set_phi_hat + sigw_spectrum compute for one realisation, with no
+ * plan: d describes the lattice and decomposition as for sigw_plan_create
+ * (n_slots, batch and autotune are ignored; the default x-pass schedule
+ * runs), phi_hat_dev is the caller's device half spectrum Phi_hat (layout and
+ * precision as sigw_set_phi_hat), the targets and shells are as in
+ * sigw_spectrum, and omega_host[n_k], nmodes_host[n_k] (either may be NULL)
+ * receive the results.  Work is enqueued on hip_stream (NULL = the null
+ * stream), which the call synchronises.
+ * Every device buffer the call needs (twiddles, kernel and lookup tables,
+ * workspace, shell partials) lives in one static array of SIGW_NOALLOC_BYTES
+ * per GPU, which that GPU holds until the process ends; the call makes no
+ * device or pinned-host allocation.  Limits: N <= 64, and the layout must
+ * fit the array: with alpha_chunk = 0 (scratch_terms = 0) the largest term
+ * count per x pass (staged terms) that fits is used, an explicit value that
+ * does not fit returns SIGW_E_INVALID.  Results agree with sigw_spectrum up
+ * to rounding (the term grouping may differ).  Every value a kernel reads is
+ * written earlier in the same call, so nothing needs to start at zero.  All
+ * calls on one GPU share its array: calls that overlap on one GPU (other host
+ * threads, other streams) race and give wrong results.  Errors as for
+ * sigw_spectrum; sigw_last_error(NULL) gives the text of this thread's last
+ * failed call. */
+#define SIGW_NOALLOC_BYTES (64u << 20)
+sigw_status sigw_spectrum_noalloc(const sigw_plan_desc* d, const void* phi_hat_dev, int32_t n_k,
+                                  const double* k_targets, const double* k_lo, const double* k_hi,
+                                  double* omega_host, int64_t* nmodes_host, void* hip_stream);
+
+const char* sigw_last_error(sigw_plan_t plan);   /* plan == NULL: the last sigw_spectrum_noalloc failure */
 const char* sigw_status_string(sigw_status s);
 
 #ifdef __cplusplus

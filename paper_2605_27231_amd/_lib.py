@@ -33,7 +33,7 @@ EXPORTS = (
     "sigw_set_timing", "sigw_kernel_time", "sigw_last_error", "sigw_status_string",
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
     "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
-    "sigw_spectrum_adaptive", "sigw_plan_set_kernel_table",
+    "sigw_spectrum_adaptive", "sigw_plan_set_kernel_table", "sigw_spectrum_noalloc",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -112,6 +112,7 @@ def lib() -> ct.CDLL:
         "sigw_plan_schedule": [P, I32, I32, ct.c_char_p, ct.c_size_t],
         "sigw_plan_set_schedule": [P, ct.c_int32],
         "sigw_plan_set_kernel_table": [P, ct.c_int32, D, D, D],
+        "sigw_spectrum_noalloc": [ct.POINTER(PlanDesc), P, ct.c_int32, D, D, D, D, I64, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -128,8 +129,7 @@ def check(status: int, plan_handle=None, what: str = "") -> None:
         return
     L = lib()
     text = L.sigw_status_string(status).decode()
-    if plan_handle:
-        detail = L.sigw_last_error(plan_handle).decode()
-        if detail:
-            text += f": {detail}"
+    detail = L.sigw_last_error(plan_handle if plan_handle else None).decode()
+    if detail:
+        text += f": {detail}"
     raise SigwError(status, f"{what}: {text}" if what else text)

@@ -70,6 +70,22 @@ def sigw_kernel_table(desc: _lib.PlanDesc, m: int):
     return sigma, phi, edges
 
 
+def sigw_spectrum_noalloc(desc: _lib.PlanDesc, phi_hat, targets, k_lo, k_hi, stream=None):
+    """Allocation-free spectrum of one realisation given as a device half
+    spectrum (torch tensor of the path's complex dtype): (omega, nmodes).
+    No plan; all device state lives in the library's static per-GPU buffer."""
+    t = np.ascontiguousarray(targets, dtype=np.float64)
+    lo = np.ascontiguousarray(k_lo, dtype=np.float64)
+    hi = np.ascontiguousarray(k_hi, dtype=np.float64)
+    om = np.zeros(len(t))
+    nb = np.zeros(len(t), dtype=np.int64)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().sigw_spectrum_noalloc(ct.byref(desc), ct.c_void_p(phi_hat.data_ptr()), len(t), _dptr(t), _dptr(lo),
+                                     _dptr(hi), _dptr(om), _i64ptr(nb), ct.c_void_p(s.cuda_stream))
+    check(st, None, "sigw_spectrum_noalloc")
+    return om, nb
+
+
 def lognormal_struct(spec) -> _lib.Lognormal:
     s = _lib.Lognormal()
     s.A, s.sigma, s.k_star = float(spec.A), float(spec.sigma), float(spec.k_star)

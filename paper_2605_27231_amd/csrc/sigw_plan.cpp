@@ -23,6 +23,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
+const char* g_noalloc_err_text();   // text of the last failed sigw_spectrum_noalloc call of this thread
+
 bool supported_N(int N) {
     switch (N) {
         case 8: case 16: case 32: case 64: case 128: case 256: case 384: case 512: return true;
@@ -760,7 +762,7 @@ const char* sigw_status_string(sigw_status s) {
     return "unknown status";
 }
 
-const char* sigw_last_error(sigw_plan_t p) { return p ? p->err.c_str() : ""; }
+const char* sigw_last_error(sigw_plan_t p) { return p ? p->err.c_str() : g_noalloc_err_text(); }
 
 sigw_status sigw_plan_desc_default(sigw_plan_desc* d, int32_t N, double L, int32_t prec) {
     if (!d) return SIGW_E_INVALID;
@@ -1537,3 +1539,206 @@ sigw_status sigw_kernel_time(sigw_plan_t p, const char* name, double* avg_ms, in
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free spectrum (sigw_spectrum_noalloc): for callers that cannot
+// allocate device memory.  Every device buffer the call needs (twiddles,
+// kernel tables, lookup tables, the per-target workspace, shell partials and
+// sums) is carved out of one static array per device, `scratch`; the host
+// code never names the array itself, only the device address that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;   // SIGW_NOALLOC_BYTES in the header
+constexpr int kNoAllocMaxN = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;        // device ordinal -> its copy of `scratch`
+thread_local std::string g_noalloc_err;    // text of the last failed no-alloc call
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+hipError_t scratch_address(int dev, char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    *out = static_cast<char*>(ptr);
+    return hipSuccess;
+}
+
+// Consecutive 256-byte aligned pieces of the scratch array; with base ==
+// nullptr it only adds up the size of a layout.
+struct Carve {
+    char* base;
+    size_t used = 0;
+    void* take(size_t bytes) {
+        const size_t o = (used + 255) & ~size_t(255);
+        used = o + bytes;
+        return base ? base + o : nullptr;
+    }
+};
+
+// Lay out every device buffer of one allocation-free spectrum of desc d with
+// `chunk` terms per x pass and `stage` staged terms, n_k targets; fills the
+// plan's device pointers when base is set.  Returns the bytes used.
+size_t noalloc_layout(sigw_plan* p, char* base, int n_k) {
+    const sigw_plan_desc& d = p->d;
+    const Sizes& z = p->z;
+    Carve c{base};
+    p->tw = c.take(size_t(d.N) * z.cb);
+    p->edges = static_cast<double*>(c.take(size_t(d.n_modes + 1) * 8));
+    for (int m = 0; m < 2; ++m) {
+        p->phi_tab[m] = c.take(size_t(d.n_modes) * d.n_alpha * z.rb);
+        p->sigma_tab[m] = c.take(size_t(d.n_alpha) * z.rb);
+    }
+    p->lut_u = static_cast<int16_t*>(c.take(size_t(z.n2max + 1) * 2));
+    p->lut_shell = static_cast<uint8_t*>(c.take(size_t(z.n2max + 1)));
+    p->T = c.take(size_t(3) * z.chunk * z.FS * z.cb);
+    p->Sst = c.take(size_t(2) * z.stage * z.FS * z.cb);
+    p->Q = c.take(size_t(12) * z.FS * z.cb);
+    const size_t zb = size_t(z.H) * d.N;
+    p->part_sum = static_cast<double*>(c.take(zb * 8));
+    p->part_cnt = static_cast<unsigned long long*>(c.take(zb * 8));
+    p->sums = static_cast<double*>(c.take(size_t(std::max(n_k, 1)) * 8));
+    p->cnts = static_cast<unsigned long long*>(c.take(size_t(std::max(n_k, 1)) * 8));
+    p->d_sel = static_cast<int*>(c.take(4));     // the slot list {0}; also the member list
+    p->d_iota = p->d_sel;
+    long fs_c = 0;
+    for (size_t i = 0; i < p->coarse.size(); ++i) {
+        const int m = kGridSizes[i];
+        p->coarse[i].tw = c.take(size_t(m) * z.cb);
+        fs_c = long(m / 2 + 1) * m * m;
+    }
+    p->phi_c = fs_c ? c.take(size_t(fs_c) * z.cb) : nullptr;
+    return c.used;
+}
+
+const char* g_noalloc_err_text() { return g_noalloc_err.c_str(); }
+
+sigw_status noalloc_fail(sigw_status s, const std::string& msg) {
+    g_noalloc_err = msg;
+    return s;
+}
+
+}  // namespace
+
+extern "C" sigw_status sigw_spectrum_noalloc(const sigw_plan_desc* d, const void* phi_hat_dev, int32_t n_k,
+                                             const double* kt, const double* lo, const double* hi,
+                                             double* omega, int64_t* nmodes, void* hip_stream) {
+    g_noalloc_err.clear();
+    if (const char* why = validate(d)) return noalloc_fail(SIGW_E_INVALID, why);
+    if (d->N > kNoAllocMaxN) return noalloc_fail(SIGW_E_INVALID, "the allocation-free spectrum takes N <= 64");
+    if (!phi_hat_dev) return noalloc_fail(SIGW_E_INVALID, "NULL Phi_hat");
+    sigw_plan P;                     // host-side state only; its device pointers point into scratch
+    P.d = *d;
+    P.d.n_slots = 1;
+    P.d.batch = 1;
+    P.stream = static_cast<hipStream_t>(hip_stream);
+    if (sigw_status s = check_targets(&P, n_k, kt, lo, hi)) return noalloc_fail(s, P.err);
+    try {
+        P.lattice_n2 = lattice_n2_table(d->N);
+        const std::shared_ptr<const Decomposition> dec = decomposition_of(*d);
+        P.edges_h = dec->edges;
+        for (int m = 0; m < 2; ++m) P.tab_h[m] = dec->tab[m];
+        for (int m : kGridSizes)
+            if (m < d->N) P.coarse.emplace_back().N = m;
+    } catch (const std::bad_alloc&) {
+        return noalloc_fail(SIGW_E_NOMEM, "host memory");
+    }
+    // Terms per x pass and staged terms: the caller's, or (0) the largest
+    // count up to n_alpha whose layout fits the array.
+    auto fits = [&](int chunk, int stage) {
+        P.d.alpha_chunk = chunk;
+        P.d.scratch_terms = stage;
+        P.z = sizes_of(P.d);
+        return noalloc_layout(&P, nullptr, n_k) <= kNoAllocBytes;
+    };
+    const int want_chunk = d->alpha_chunk, want_stage = d->scratch_terms;
+    int chunk = want_chunk ? want_chunk : d->n_alpha;
+    while (chunk > 1 && !fits(chunk, want_stage ? std::min(want_stage, chunk) : 1) && !want_chunk) --chunk;
+    int stage = want_stage ? std::min(want_stage, chunk) : chunk;
+    while (stage > 1 && !fits(chunk, stage) && !want_stage) --stage;
+    if (!fits(chunk, stage))
+        return noalloc_fail(SIGW_E_INVALID, "this lattice, precision and term counts need more than the " +
+                                                std::to_string(kNoAllocBytes >> 20) +
+                                                " MiB of the allocation-free buffer (lower alpha_chunk or scratch_terms)");
+    // only now touch the device: the address of its copy of the array
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return noalloc_fail(SIGW_E_DEVICE, "hipGetDevice failed");
+    char* base = nullptr;
+    if (hipError_t e = scratch_address(dev, &base); e != hipSuccess)
+        return noalloc_fail(SIGW_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    noalloc_layout(&P, base, n_k);
+    P.phi_hat = const_cast<void*>(phi_hat_dev);
+    P.has_field.assign(1, 1);
+    // tables in the path precision, twiddles, the slot list {0}
+    const Sizes& z = P.z;
+    std::vector<char> twh(size_t(d->N) * z.cb), phih[2], sigh[2];
+    sigw::host_twiddles(d->prec, d->N, twh.data());
+    std::vector<std::vector<char>> twc(P.coarse.size());
+    for (size_t i = 0; i < P.coarse.size(); ++i) {
+        twc[i].resize(size_t(P.coarse[i].N) * z.cb);
+        sigw::host_twiddles(d->prec, P.coarse[i].N, twc[i].data());
+    }
+    for (int m = 0; m < 2; ++m) {
+        const Table& t = P.tab_h[m];
+        phih[m].resize(t.phi.size() * z.rb);
+        sigh[m].resize(t.sigma.size() * z.rb);
+        for (size_t i = 0; i < t.phi.size(); ++i) {
+            if (d->prec == SIGW_F64) reinterpret_cast<double*>(phih[m].data())[i] = t.phi[i];
+            else reinterpret_cast<float*>(phih[m].data())[i] = float(t.phi[i]);
+        }
+        for (size_t i = 0; i < t.sigma.size(); ++i) {
+            if (d->prec == SIGW_F64) reinterpret_cast<double*>(sigh[m].data())[i] = t.sigma[i];
+            else reinterpret_cast<float*>(sigh[m].data())[i] = float(t.sigma[i]);
+        }
+    }
+    const int zero = 0;
+    hipStream_t s = P.stream;
+    bool ok = hipMemcpyAsync(P.tw, twh.data(), twh.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(P.edges, P.edges_h.data(), P.edges_h.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(P.d_sel, &zero, 4, hipMemcpyHostToDevice, s) == hipSuccess;
+    for (int m = 0; m < 2 && ok; ++m)
+        ok = hipMemcpyAsync(P.phi_tab[m], phih[m].data(), phih[m].size(), hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(P.sigma_tab[m], sigh[m].data(), sigh[m].size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    for (size_t i = 0; i < P.coarse.size() && ok; ++i)
+        ok = hipMemcpyAsync(P.coarse[i].tw, twc[i].data(), twc[i].size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!ok) {
+        (void)hipStreamSynchronize(s);
+        return noalloc_fail(SIGW_E_DEVICE, "table upload failed");
+    }
+    P.eng.reset(sigw::make_engine(d->prec, d->N, P.tw));
+    for (auto& c : P.coarse) c.eng.reset(sigw::make_engine(d->prec, c.N, c.tw));
+    bool made = bool(P.eng);
+    for (auto& c : P.coarse) made = made && bool(c.eng);
+    if (!made) {
+        (void)hipStreamSynchronize(s);
+        return noalloc_fail(SIGW_E_UNSUPPORTED, "no compiled schedule for this size");
+    }
+    std::vector<int> valid;
+    sigw_status st = enqueue_spectrum(&P, P.d_sel, 1, n_k, kt, lo, hi, P.sums, P.cnts, valid, false);
+    std::vector<double> hs(size_t(std::max(n_k, 1)), 0.0);
+    std::vector<unsigned long long> hc(size_t(std::max(n_k, 1)), 0ull);
+    if (st == SIGW_OK && n_k > 0 &&
+        (hipMemcpyAsync(hs.data(), P.sums, size_t(n_k) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipMemcpyAsync(hc.data(), P.cnts, size_t(n_k) * 8, hipMemcpyDeviceToHost, s) != hipSuccess))
+        st = fail(&P, SIGW_E_DEVICE, "result copies failed");
+    // the host tables above must outlive their copies: wait for the stream in every case
+    const hipError_t es = hipStreamSynchronize(s);
+    if (st != SIGW_OK) return noalloc_fail(st, P.err);
+    if (es != hipSuccess) return noalloc_fail(SIGW_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(es));
+    to_omega(&P, n_k, kt, hs.data(), hc.data(), valid.data(), omega, nmodes);
+    return SIGW_OK;
+}

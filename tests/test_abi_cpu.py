@@ -128,3 +128,30 @@ def test_new_entry_points_reject_null_plans():
         _lib.SIGW_E_INVALID
     assert L.sigw_spectrum_adaptive(None, 0, 0, None, None, 0, None, 0.1, None, None, None) == \
         _lib.SIGW_E_INVALID
+
+
+def test_noalloc_rejects_before_touching_the_device():
+    """The allocation-free spectrum validates on the host: N above 64, a NULL
+    Phi_hat, bad shells and an explicit term count whose layout exceeds the
+    static buffer are refused with SIGW_E_INVALID and a text, with no device
+    call (there is no GPU here)."""
+    L = _lib.lib()
+    D = ct.POINTER(ct.c_double)
+    t = np.array([3.0])
+    lo, hi = t - 0.5, t + 0.5
+    om = np.zeros(1)
+    nb = np.zeros(1, dtype=np.int64)
+    args = lambda: (t.ctypes.data_as(D), lo.ctypes.data_as(D), hi.ctypes.data_as(D), om.ctypes.data_as(D),
+                    nb.ctypes.data_as(ct.POINTER(ct.c_int64)), None)
+    fake = ct.c_void_p(16)     # never dereferenced: every case fails validation first
+    d = P.plan_desc(128)
+    assert L.sigw_spectrum_noalloc(ct.byref(d), fake, 1, *args()) == _lib.SIGW_E_INVALID
+    assert b"N <= 64" in L.sigw_last_error(None)
+    d = P.plan_desc(64)
+    assert L.sigw_spectrum_noalloc(ct.byref(d), None, 1, *args()) == _lib.SIGW_E_INVALID
+    bad_hi = np.array([2.0])
+    assert L.sigw_spectrum_noalloc(ct.byref(d), fake, 1, t.ctypes.data_as(D), lo.ctypes.data_as(D),
+                                   bad_hi.ctypes.data_as(D), None, None, None) == _lib.SIGW_E_INVALID
+    d = P.plan_desc(64, prec="f64", alpha_chunk=50)     # 150 + 100 + 12 half spectra of 2.2 MB
+    assert L.sigw_spectrum_noalloc(ct.byref(d), fake, 1, *args()) == _lib.SIGW_E_INVALID
+    assert b"MiB" in L.sigw_last_error(None)
