@@ -417,6 +417,24 @@ def quick_profile():
                       "nmodes": int(nb[0]), "copy_bytes": 1 << 30}), flush=True)
 
 
+def stream_probe():
+    """The streaming-rate probe (sigw_stream_probe): read, write, copy and the
+    2-read : 3-write mix over 1 GiB arrays, fastest of 5 launches each, three
+    times; prints one JSON line."""
+    import torch
+    from paper_2605_27231_amd import api
+
+    names = ("read", "write", "copy", "mix_2r3w")
+    res = {n: [] for n in names}
+    for _ in range(3):
+        for k, n in enumerate(names):
+            res[n].append(round(api.sigw_stream_probe(k, 1 << 30, 5), 1))
+    torch.cuda.synchronize()
+    print(json.dumps({"stream_probe_GB_s": res, "array_bytes": 1 << 30,
+                      "what": "fastest of 5 launches per kind, 3 rounds; bytes = arrays touched x 1 GiB"}),
+          flush=True)
+
+
 def cpu_baseline(budget_terms=(1, 6)):
     """The FP64 oracle on a bounded sample: field generation of seed 0, then the
     source convolutions of the sine kernel at the peak target with 1 and 6 of
@@ -466,9 +484,14 @@ def main():
                     help="one field + one target + a 1 GiB copy, for hardware-counter passes")
     ap.add_argument("--workload", default="local256", choices=sorted(WORKLOADS),
                     help="local256 (the headline line) or exptail512")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only the streaming-rate probe (read, write, copy, 2-read:3-write)")
     args = ap.parse_args()
     if args.quick:
         quick_profile()
+        return
+    if args.stream_probe:
+        stream_probe()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU mode.  Realisations and "

@@ -134,6 +134,23 @@ sigw_status sigw_plan_destroy(sigw_plan_t plan);
 sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma, double* phi,
                               double* edges);
 
+/* Host-only table of the same layout for a background of constant equation
+ * of state w, 0 < w < 1, with adiabatic pressure (c_s^2 = w): the kernels
+ * I_m^w(u, v) are the asymptotic envelope time integrals of Sec. IV with
+ * Sec. II's ingredients for that background (Eq. scalar and the homogeneous
+ * wave equation solved by Bessel functions, the Wronskian from Abel's
+ * identity, the 2/(3(1+w)) source factor), including the factor
+ * [3(1+w)/(5+3w) / (2/3)]^2 that converts the initial potential of Sec. II
+ * to the Phi = 2 zeta / 3 the lattice path carries.  At w = 1/3 they are
+ * Eq. kernels.  Decomposed on the grid of d as in Sec. V; install with
+ * sigw_plan_set_kernel_table (both m).  The Omega normalisation of Sec. III
+ * is the radiation-era one; for w != 1/3 the spectrum returned is that
+ * expression evaluated with these envelopes.  Takes seconds the first time
+ * for each (grid, w) in the process (cached).  SIGW_E_INVALID for m not in
+ * {0, 1}, w outside (0, 1), or sqrt(w) u_min below ~1e-3. */
+sigw_status sigw_kernel_table_w(const sigw_plan_desc* d, double w, int32_t m, double* sigma, double* phi,
+                                double* edges);
+
 /* Replace kernel m's separable table in a plan with the caller's own, in the
  * layout sigw_kernel_table returns: sigma[n_alpha], phi[n_modes * n_alpha]
  * (phi_a on interval i at phi[i * n_alpha + a]) and, unless NULL, the u grid
@@ -293,6 +310,19 @@ sigw_status sigw_graph_destroy(sigw_graph_t graph);
 sigw_status sigw_autotune(sigw_plan_t plan, int32_t flags);
 sigw_status sigw_plan_schedule(sigw_plan_t plan, int32_t* index, int32_t* count, char* text, size_t text_len);
 sigw_status sigw_plan_set_schedule(sigw_plan_t plan, int32_t index);
+
+/* Streaming-rate probe, a measurement aid (not a step of the method): the
+ * device-memory rate of a plain kernel of one of four access patterns, the
+ * achievable figures the hot kernels' HBM fractions are read against.
+ * kind 0: read one array (float4 loads, a sum per block), 1: write one array,
+ * 2: copy one array into a second, 3: read two arrays and write three (the
+ * y-pass kernel's mix).  bytes is the size of one array (a multiple of 16,
+ * at least 32 MiB); buf_dev must hold (1, 1, 2, 5 arrays for kind 0..3) x
+ * bytes plus 32 KiB (the read's block sums).  One warm-up launch, then the
+ * fastest of reps launches timed with HIP events on hip_stream (NULL = the
+ * null stream); *gb_per_s = arrays x bytes / time.  Synchronises. */
+sigw_status sigw_stream_probe(int32_t kind, void* buf_dev, size_t bytes, int32_t reps, void* hip_stream,
+                              double* gb_per_s);
 
 /* Block until the plan stream is idle. */
 sigw_status sigw_synchronize(sigw_plan_t plan);

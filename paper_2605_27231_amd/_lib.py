@@ -34,6 +34,7 @@ EXPORTS = (
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
     "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
     "sigw_spectrum_adaptive", "sigw_plan_set_kernel_table", "sigw_spectrum_noalloc",
+    "sigw_kernel_table_w", "sigw_stream_probe",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -86,6 +87,8 @@ def lib() -> ct.CDLL:
         "sigw_plan_create": [ct.POINTER(PlanDesc), P, ct.POINTER(P)],
         "sigw_plan_destroy": [P],
         "sigw_kernel_table": [ct.POINTER(PlanDesc), ct.c_int32, D, D, D],
+        "sigw_kernel_table_w": [ct.POINTER(PlanDesc), ct.c_double, ct.c_int32, D, D, D],
+        "sigw_stream_probe": [ct.c_int32, P, ct.c_size_t, ct.c_int32, P, D],
         "sigw_white_noise": [P, ct.c_uint64, P],
         "sigw_generate_field": [P, ct.c_int32, ct.c_uint64, ct.POINTER(Lognormal), ct.POINTER(NGMap)],
         "sigw_set_zeta": [P, ct.c_int32, P],

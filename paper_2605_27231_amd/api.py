@@ -70,6 +70,31 @@ def sigw_kernel_table(desc: _lib.PlanDesc, m: int):
     return sigma, phi, edges
 
 
+def sigw_stream_probe(kind: int, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s of the streaming probe kind (0 read, 1 write, 2 copy, 3 2-read:3-write)
+    over arrays of nbytes each, in a buffer that torch allocates."""
+    arrays = (1, 1, 2, 5)[kind]
+    buf = torch.empty(arrays * nbytes + (32 << 10), dtype=torch.uint8, device="cuda")
+    buf.zero_()
+    out = ct.c_double(0.0)
+    s = torch.cuda.current_stream()
+    check(lib().sigw_stream_probe(int(kind), ct.c_void_p(buf.data_ptr()), nbytes, int(reps),
+                                  ct.c_void_p(s.cuda_stream), ct.byref(out)), None, "sigw_stream_probe")
+    del buf
+    return out.value
+
+
+def sigw_kernel_table_w(desc: _lib.PlanDesc, w: float, m: int):
+    """Host-only table for a constant equation of state w:
+    (sigma[n_alpha], phi[n_modes, n_alpha], edges[n_modes+1])."""
+    sigma = np.zeros(desc.n_alpha)
+    phi = np.zeros((desc.n_modes, desc.n_alpha))
+    edges = np.zeros(desc.n_modes + 1)
+    check(lib().sigw_kernel_table_w(ct.byref(desc), float(w), m, _dptr(sigma), _dptr(phi), _dptr(edges)),
+          None, "sigw_kernel_table_w")
+    return sigma, phi, edges
+
+
 def sigw_spectrum_noalloc(desc: _lib.PlanDesc, phi_hat, targets, k_lo, k_hi, stream=None):
     """Allocation-free spectrum of one realisation given as a device half
     spectrum (torch tensor of the path's complex dtype): (omega, nmodes).
@@ -265,6 +290,12 @@ class Plan:
         self._chk(lib().sigw_plan_set_kernel_table(self.h, int(m), _dptr(s), _dptr(f),
                                                    None if e is None else _dptr(e)),
                   "sigw_plan_set_kernel_table")
+
+    def set_equation_of_state(self, w: float):
+        """Install the kernel tables of a constant equation of state w (both
+        kernels, on this plan's grid)."""
+        for m in (0, 1):
+            self.set_kernel_table(m, *sigw_kernel_table_w(self.desc, w, m))
 
     # -- x-pass schedule ------------------------------------------------------
     def autotune(self, force: bool = False) -> str:

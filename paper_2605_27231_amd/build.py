@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsigw.so")
 
-SOURCES = ["sigw_plan.cpp", "sigw_kernels.hip"]
+SOURCES = ["sigw_plan.cpp", "sigw_kernels.hip", "sigw_eos.cpp", "sigw_probe.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -18,6 +18,7 @@
 
 #include "../../include/sigw.h"
 #include "sigw_engine.hpp"
+#include "sigw_eos.hpp"
 
 namespace {
 
@@ -129,23 +130,13 @@ struct Table {
     std::vector<double> phi;     // n_modes x n_alpha
 };
 
-// Sec. V: C_ij = sqrt(L_i L_j) I(c_i, c_j) on |c_i - c_j| <= 1 <= c_i + c_j
-// (the triangle u, v and the unit k close), diagonalised; the n_alpha terms
-// of largest |sigma| are kept with their signs; phi_a = q_a,i / sqrt(L_i).
-Table build_table(const sigw_plan_desc& d, const std::vector<double>& e, int m) {
+// Sec. V: the kernel matrix C (n_modes x n_modes, row-major) diagonalised;
+// the n_alpha terms of largest |sigma| are kept with their signs;
+// phi_a = q_a,i / sqrt(L_i).
+Table decompose_matrix(const sigw_plan_desc& d, const std::vector<double>& e, std::vector<double> A) {
     const int M = d.n_modes;
-    std::vector<double> c(M), L(M);
-    for (int i = 0; i < M; ++i) {
-        c[i] = 0.5 * (e[i] + e[i + 1]);
-        L[i] = e[i + 1] - e[i];
-    }
-    std::vector<double> A(size_t(M) * M, 0.0);
-    for (int i = 0; i < M; ++i)
-        for (int j = 0; j < M; ++j) {
-            const double u = c[i], v = c[j];
-            if (std::fabs(u - v) <= 1.0 && u + v >= 1.0)
-                A[size_t(i) * M + j] = std::sqrt(L[i] * L[j]) * (m == 0 ? kernel_s(u, v) : kernel_c(u, v));
-        }
+    std::vector<double> L(M);
+    for (int i = 0; i < M; ++i) L[i] = e[i + 1] - e[i];
     std::vector<double> V;
     jacobi_eigen(A, V, M);
     std::vector<int> order(M);
@@ -162,6 +153,54 @@ Table build_table(const sigw_plan_desc& d, const std::vector<double>& e, int m) 
         for (int i = 0; i < M; ++i) t.phi[size_t(i) * d.n_alpha + a] = V[size_t(i) * M + k] / std::sqrt(L[i]);
     }
     return t;
+}
+
+// Interval centres c_i and the strip mask |c_i - c_j| <= 1 <= c_i + c_j (the
+// triangle that u, v and the unit k close, Sec. V)
+void centres_and_strip(const sigw_plan_desc& d, const std::vector<double>& e, std::vector<double>& c,
+                       std::vector<unsigned char>& strip) {
+    const int M = d.n_modes;
+    c.resize(M);
+    for (int i = 0; i < M; ++i) c[i] = 0.5 * (e[i] + e[i + 1]);
+    strip.assign(size_t(M) * M, 0);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) strip[size_t(i) * M + j] = std::fabs(c[i] - c[j]) <= 1.0 && c[i] + c[j] >= 1.0;
+}
+
+// Sec. V: C_ij = sqrt(L_i L_j) I(c_i, c_j) on the strip (Eq. C_matrix_discrete)
+// with the radiation-era kernels of Eq. kernels, decomposed.
+Table build_table(const sigw_plan_desc& d, const std::vector<double>& e, int m) {
+    const int M = d.n_modes;
+    std::vector<double> c;
+    std::vector<unsigned char> strip;
+    centres_and_strip(d, e, c, strip);
+    std::vector<double> A(size_t(M) * M, 0.0);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j)
+            if (strip[size_t(i) * M + j])
+                A[size_t(i) * M + j] = std::sqrt((e[i + 1] - e[i]) * (e[j + 1] - e[j])) *
+                                       (m == 0 ? kernel_s(c[i], c[j]) : kernel_c(c[i], c[j]));
+    return decompose_matrix(d, e, std::move(A));
+}
+
+// The same with the kernels of a constant equation of state w (sigw_eos.cpp):
+// both tables from one evaluation of the time integrals on the strip.
+void build_tables_w(const sigw_plan_desc& d, const std::vector<double>& e, double w, Table out[2]) {
+    const int M = d.n_modes;
+    std::vector<double> c;
+    std::vector<unsigned char> strip;
+    centres_and_strip(d, e, c, strip);
+    std::vector<double> Is(size_t(M) * M, 0.0), Ic(size_t(M) * M, 0.0);
+    sigw::eos_kernel_matrices(w, c.data(), M, strip.data(), Is.data(), Ic.data());
+    for (int m = 0; m < 2; ++m) {
+        std::vector<double> A(size_t(M) * M, 0.0);
+        const std::vector<double>& I = m == 0 ? Is : Ic;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j)
+                if (strip[size_t(i) * M + j])
+                    A[size_t(i) * M + j] = std::sqrt((e[i + 1] - e[i]) * (e[j + 1] - e[j])) * I[size_t(i) * M + j];
+        out[m] = decompose_matrix(d, e, std::move(A));
+    }
 }
 
 // The tables depend only on the decomposition meta-parameters, and building
@@ -187,6 +226,25 @@ std::shared_ptr<const Decomposition> decomposition_of(const sigw_plan_desc& d) {
     for (int m = 0; m < 2; ++m) dec->tab[m] = build_table(d, dec->edges, m);
     std::lock_guard<std::mutex> lk(g_decomp_mu);
     return g_decomp.emplace(key, std::move(dec)).first->second;
+}
+
+// Constant-w tables, built once per (meta-parameters, w) in the process: the
+// time integrals take seconds.
+using DecompKeyW = std::tuple<int, int, double, double, double, double, double, double>;
+std::map<DecompKeyW, std::shared_ptr<const Decomposition>> g_decomp_w;
+
+std::shared_ptr<const Decomposition> decomposition_w_of(const sigw_plan_desc& d, double w) {
+    const DecompKeyW key{d.n_modes, d.n_alpha, d.u_min, d.u_max, d.u_p, d.sigma_p, d.A_p, w};
+    {
+        std::lock_guard<std::mutex> lk(g_decomp_mu);
+        auto it = g_decomp_w.find(key);
+        if (it != g_decomp_w.end()) return it->second;
+    }
+    auto dec = std::make_shared<Decomposition>();
+    dec->edges = grid_edges(d);
+    build_tables_w(d, dec->edges, w, dec->tab);
+    std::lock_guard<std::mutex> lk(g_decomp_mu);
+    return g_decomp_w.emplace(key, std::move(dec)).first->second;
 }
 
 const char* validate(const sigw_plan_desc* d) {
@@ -801,6 +859,25 @@ sigw_status sigw_kernel_table(const sigw_plan_desc* d, int32_t m, double* sigma,
         if (phi) std::copy(t.phi.begin(), t.phi.end(), phi);
     } catch (const std::bad_alloc&) {
         return SIGW_E_NOMEM;
+    }
+    return SIGW_OK;
+}
+
+sigw_status sigw_kernel_table_w(const sigw_plan_desc* d, double w, int32_t m, double* sigma, double* phi,
+                                double* edges) {
+    if (validate(d) || (m != 0 && m != 1) || !(w > 0.0 && w < 1.0)) return SIGW_E_INVALID;
+    try {
+        const std::shared_ptr<const Decomposition> dec = decomposition_w_of(*d, w);
+        if (edges) std::copy(dec->edges.begin(), dec->edges.end(), edges);
+        const Table& t = dec->tab[m];
+        for (double s : t.sigma)
+            if (!std::isfinite(s)) return SIGW_E_INVALID;
+        if (sigma) std::copy(t.sigma.begin(), t.sigma.end(), sigma);
+        if (phi) std::copy(t.phi.begin(), t.phi.end(), phi);
+    } catch (const std::bad_alloc&) {
+        return SIGW_E_NOMEM;
+    } catch (const std::exception&) {
+        return SIGW_E_INVALID;
     }
     return SIGW_OK;
 }

@@ -155,3 +155,30 @@ def test_noalloc_rejects_before_touching_the_device():
     d = P.plan_desc(64, prec="f64", alpha_chunk=50)     # 150 + 100 + 12 half spectra of 2.2 MB
     assert L.sigw_spectrum_noalloc(ct.byref(d), fake, 1, *args()) == _lib.SIGW_E_INVALID
     assert b"MiB" in L.sigw_last_error(None)
+
+
+def test_library_constant_w_tables_match_oracle():
+    """f4 on the library side: the C++ constant-w builder (series and
+    asymptotic expansions, an ODE for y1, its own quadratures) against the
+    oracle's tables (SciPy Bessel and Hankel functions, its own quadratures):
+    the kept kernels sum_a sigma_a phi_a phi_a agree to 1e-7 of their
+    largest value; at w = 1/3 the library's table is its closed-form one."""
+    from oracle import eos
+    d = P.plan_desc(64)
+    for w in (0.6,):
+        ref = eos.tables_w(w)
+        for m in (0, 1):
+            s, phi, e = P.sigw_kernel_table_w(d, w, m)
+            np.testing.assert_allclose(e, ref[m].edges, rtol=1e-14)     # libm vs SciPy erf: an ulp
+            K = (phi * s) @ phi.T
+            K0 = (ref[m].phi * ref[m].sigma) @ ref[m].phi.T
+            assert np.abs(K - K0).max() <= 1e-7 * np.abs(K0).max(), (w, m)
+    for m in (0, 1):
+        s, phi, _ = P.sigw_kernel_table_w(d, 1.0 / 3.0, m)
+        s0, phi0, _ = P.sigw_kernel_table(d, m)
+        K, K0 = (phi * s) @ phi.T, (phi0 * s0) @ phi0.T
+        assert np.abs(K - K0).max() <= 1e-8 * np.abs(K0).max()
+    L = _lib.lib()
+    D = ct.POINTER(ct.c_double)
+    for bad_w in (0.0, 1.0, -0.2, float("nan")):
+        assert L.sigw_kernel_table_w(ct.byref(d), bad_w, 0, None, None, None) == _lib.SIGW_E_INVALID

@@ -8,7 +8,12 @@ another kernel, e.g. one from another equation of state).
   against 4), decomposed by the oracle: FP64 path within 1e-10 and FP32
   path within 1e-4 per bin of the oracle's spectrum with the same tables
   (the support bound must follow the new grid, or modes would be dropped);
-* invalid tables are refused and leave the plan unchanged.
+* invalid tables are refused and leave the plan unchanged;
+* the tables of a constant equation of state (w = 0.6; Sec. II equations,
+  Sec. IV time integrals), built by the oracle and installed: FP64 within
+  1e-10 and FP32 within 1e-4 per bin of the oracle's spectrum with the same
+  tables; the library's own constant-w tables (Plan.set_equation_of_state)
+  within 1e-6 of it (the two builders agree to ~1e-8 in the kept kernel).
 """
 import math
 
@@ -16,7 +21,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import decomposition, field, spectrum
+from oracle import decomposition, eos, field, spectrum
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +101,33 @@ def test_invalid_tables_refused():
                 pl.set_kernel_table(*args)
         om1, _ = pl.spectrum(0, job.targets, job.k_lo, job.k_hi)
     np.testing.assert_array_equal(om0.view(np.uint64), om1.view(np.uint64))
+
+
+@pytest.fixture(scope="module")
+def tabs_w06():
+    return eos.tables_w(0.6)
+
+
+@pytest.mark.parametrize("N,prec,tol", [(32, "f64", 1e-10), (64, "f32", 1e-4)])
+def test_constant_w_tables_vs_oracle(N, prec, tol, tabs_w06):
+    job = _job(N)
+    ph = field.phi_hat(N, job.L, 5, job.spectrum, job.ngmap)
+    _say(f"constant-w (0.6) tables N={N} prec={prec}")
+    ref, nref = spectrum.omega_spectrum(ph, tabs_w06[0], tabs_w06[1], job.targets, job.k_lo, job.k_hi, job.L)
+    ok = nref > 0
+    assert ok.sum() >= 8
+    with P.Plan(N, prec=prec) as pl:
+        pl.generate_field(0, 5, job.spectrum, job.ngmap)
+        for m in range(2):
+            pl.set_kernel_table(m, tabs_w06[m].sigma, tabs_w06[m].phi, tabs_w06[m].edges)
+        got, nb = pl.spectrum(0, job.targets, job.k_lo, job.k_hi)
+        np.testing.assert_array_equal(nb, nref)
+        rel = np.abs(got[ok] - ref[ok]) / np.abs(ref[ok])
+        _say("  oracle tables: max rel err per bin", rel.max())
+        assert rel.max() <= tol
+        pl.set_equation_of_state(0.6)          # the library's own builder
+        got2, nb2 = pl.spectrum(0, job.targets, job.k_lo, job.k_hi)
+    np.testing.assert_array_equal(nb2, nref)
+    rel2 = np.abs(got2[ok] - ref[ok]) / np.abs(ref[ok])
+    _say("  library tables: max rel err per bin", rel2.max())
+    assert rel2.max() <= max(tol, 1e-6)
