@@ -391,21 +391,22 @@ def run_gpu(args):
     return res
 
 
-def quick_profile():
+def quick_profile(workload: str = "local256"):
     """A short run for hardware-counter passes, in the benchmark's launch
-    configuration and launch mix: the four 256^3 fields in one batch through
-    every target of the spectrum (one step, so the per-launch averages of the
-    counters cover the same launches as the benchmark's), and a plain 1 GiB
-    device copy whose counter readings calibrate the byte counters (read
-    1 GiB, write 1 GiB)."""
+    configuration and launch mix: local256: the four 256^3 fields in one
+    batch through every target of the spectrum (one step, so the per-launch
+    averages of the counters cover the same launches as the benchmark's);
+    exptail512: one 512^3 realisation (the benchmark runs them one at a time)
+    through every target; then a plain 1 GiB device copy whose counter
+    readings calibrate the byte counters (read 1 GiB, write 1 GiB)."""
     import torch
     import paper_2605_27231_amd as P
 
-    job = W.config_local_ng(256, 64)
+    job = WORKLOADS[workload]["job"]()
     b = int(np.argmin(np.abs(job.targets - job.spectrum.k_star * 2 / math.sqrt(3))))
-    n = len(job.seeds)
+    n = len(job.seeds) if job.N <= 256 else 1
     with P.Plan(job.N, L=job.L, prec="f32", n_slots=n, batch=n, autotune=1) as plan:
-        for i, s in enumerate(job.seeds):
+        for i, s in enumerate(job.seeds[:n]):
             plan.generate_field(i, s, job.spectrum, job.ngmap)
         om, nb = plan.spectrum_batch(list(range(n)), job.targets, job.k_lo, job.k_hi)
         om, nb = om[0][b:b + 1], nb[0][b:b + 1]
@@ -488,7 +489,7 @@ def main():
                     help="only the streaming-rate probe (read, write, copy, 2-read:3-write)")
     args = ap.parse_args()
     if args.quick:
-        quick_profile()
+        quick_profile(args.workload)
         return
     if args.stream_probe:
         stream_probe()

@@ -6,7 +6,10 @@
               * [ (ln|(3-q^2)/(3-s^2)| + 2(s^2-q^2)/(q^2+s^2-6))^2 + pi^2 Theta(s - sqrt3) ]
 
 The s integral is split at the logarithmic singularity s = sqrt(3) and cut
-where the log-normal factors have decayed below double precision.
+where the log-normal factors have decayed below double precision.  Above
+sqrt(3) it can be split further into `pieces` geometric intervals, which a
+narrow (sigma = 0.1) or wide (sigma = 1) peak needs for the adaptive
+quadrature to find all of its weight; the result must not depend on it.
 """
 from __future__ import annotations
 
@@ -30,14 +33,15 @@ def T_kernel(q, s):
         return 12.0 * (q2 + s2 - 6.0) ** 4 / (s2 - q2) ** 8 * (q2 - 1.0) ** 2 * (s2 - 1.0) ** 2 * br
 
 
-def omega_gauss(k: float, A: float, sigma: float, k_star: float, epsrel: float = 1e-8) -> float:
+def omega_gauss(k: float, A: float, sigma: float, k_star: float, epsrel: float = 1e-8, pieces: int = 1) -> float:
     def f(s, q):
         return float(T_kernel(q, s) * lognormal_delta2(k * (s + q) / 2.0, A, sigma, k_star)
                      * lognormal_delta2(k * (s - q) / 2.0, A, sigma, k_star))
     # beyond s_max both Delta^2 factors are below exp(-40) of their peak
     s_max = max(2.0 * k_star / k * math.exp(9.0 * sigma) + 1.0, SQRT3 + 1.0)
+    cuts = [SQRT3] + list(np.geomspace(SQRT3, s_max, pieces + 1)[1:])
     total = 0.0
-    for a, b in ((1.0, SQRT3), (SQRT3, s_max)):
+    for a, b in [(1.0, SQRT3)] + list(zip(cuts[:-1], cuts[1:])):
         val, _ = integrate.dblquad(f, 0.0, 1.0, lambda q: a, lambda q: b,
                                    epsabs=0.0, epsrel=epsrel)
         total += val

@@ -44,12 +44,15 @@ class Served:
 
 
 class GpuBackend:
-    """Plans of the HIP library, one stream each.  Large lattices use fewer
-    terms per workspace pass (alpha_chunk) to keep several plans resident."""
+    """Plans of the HIP library, one stream each.  The largest lattices use
+    fewer terms per workspace pass (alpha_chunk) so that several plans stay
+    resident: at 384^3, 25 terms per pass cost 3% more time per request than
+    all 50 (54 GB plans) and 10 terms cost 15%; at 256^3 and below every term
+    shares one pass (measured with --service-times)."""
 
     def __init__(self, prec: str = "f32", chunk_for=None):
         self.prec = prec
-        self.chunk_for = chunk_for or (lambda N: 10 if N >= 256 else 0)
+        self.chunk_for = chunk_for or (lambda N: 25 if N >= 384 else 0)
 
     def _desc(self, N):
         from .api import plan_desc
@@ -228,6 +231,42 @@ def summarize(done: List[Served], wall: float) -> dict:
     }
 
 
+def service_times(sizes, chunks, prec: str = "f32", reps: int = 3, n_targets: int = 4) -> dict:
+    """Device time of one request of each lattice size run alone (field
+    generation + n_targets thin shells around the peak), for each alpha_chunk
+    in chunks: the per-size service times that bound the served rate.  The
+    capacity at the stream's N mix is 1 / sum_N weight_N t_N."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import torch
+    import workloads as W
+    from .api import Plan, plan_desc, sigw_plan_footprint
+
+    out = {}
+    for N in sizes:
+        req = next(r for r in W.request_stream(400, 50.0, sizes=sizes) if r.job.N == N)
+        job = req.job
+        for ch in chunks:
+            fp = sigw_plan_footprint(plan_desc(N, prec=prec, alpha_chunk=ch))
+            with Plan(N, prec=prec, alpha_chunk=ch, autotune=1) as pl:
+                ts = []
+                for r in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    pl.generate_field(0, int(job.seeds[0]), job.spectrum, job.ngmap)
+                    pl.spectrum(0, job.targets, job.k_lo, job.k_hi)
+                    torch.cuda.synchronize()
+                    if r:
+                        ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            out[f"{N}/chunk{ch}"] = {"N": N, "alpha_chunk": ch, "ms_per_request": round(t * 1e3, 3),
+                                     "ms_per_target": round(t * 1e3 / n_targets, 3), "plan_GB": round(fp / 1e9, 2)}
+            print(f"[service] N={N} alpha_chunk={ch}: {t * 1e3:.2f} ms per request ({fp / 1e9:.1f} GB plan)",
+                  file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     import sys
     import os
@@ -243,10 +282,22 @@ def main():
     ap.add_argument("--sizes", default="64,128,256,384")
     ap.add_argument("--max-inflight", type=int, default=8)
     ap.add_argument("--plans-per-size", type=int, default=4)
+    ap.add_argument("--service-times", action="store_true",
+                    help="only time one request of each size alone, at alpha_chunk 0 / 10 / 25")
     args = ap.parse_args()
     sizes = tuple(int(s) for s in args.sizes.split(","))
     weights = {64: 0.4, 128: 0.3, 256: 0.2, 384: 0.1}
     w = np.array([weights.get(n, 1.0) for n in sizes])
+    if args.service_times:
+        st = service_times(sizes, (0, 10, 25), args.prec)
+        best = {N: min(v["ms_per_request"] for v in st.values() if v["N"] == N) for N in sizes}
+        mean = float(sum(wt * best[N] for N, wt in zip(sizes, w / w.sum())))
+        print(json.dumps({"service": st, "best_ms_per_request": best, "mean_ms_at_mix": round(mean, 3),
+                          "capacity_req_per_s": round(1e3 / mean, 2),
+                          "what": "one request (field + 4 thin shells) alone per size; capacity = 1 / mean "
+                                  "service time at the stream's N mix with the fastest chunking per size"}),
+              flush=True)
+        return
     reqs = W.request_stream(args.requests, args.rate, sizes=sizes, weights=tuple(w / w.sum()))
     backend = GpuBackend(args.prec)
     prewarm = {64: 4, 128: 4, 256: 3, 384: 2}
