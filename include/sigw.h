@@ -311,6 +311,16 @@ sigw_status sigw_autotune(sigw_plan_t plan, int32_t flags);
 sigw_status sigw_plan_schedule(sigw_plan_t plan, int32_t* index, int32_t* count, char* text, size_t text_len);
 sigw_status sigw_plan_set_schedule(sigw_plan_t plan, int32_t index);
 
+/* Host-only: the modes of the N^3 lattice (box L) in the shell
+ * k_lo <= k_F |n| < k_hi, n != 0 (Sec. IV shell estimator), as sigw_spectrum
+ * counts them: *count = N_b, and [*n2_lo, *n2_hi] the range of |n|^2 over
+ * them (either pointer may be NULL; untouched when *count = 0).  The shell
+ * test is the FP64 k_F sqrt(|n|^2) the device lookup tables use; k_lo may be
+ * negative and k_hi arbitrarily large.  SIGW_E_INVALID for an unsupported N,
+ * L <= 0, non-finite edges, k_hi <= k_lo or count == NULL. */
+sigw_status sigw_shell_modes(int32_t N, double L, double k_lo, double k_hi, int32_t* n2_lo, int32_t* n2_hi,
+                             int64_t* count);
+
 /* Streaming-rate probe, a measurement aid (not a step of the method): the
  * device-memory rate of a plain kernel of one of four access patterns, the
  * achievable figures the hot kernels' HBM fractions are read against.

@@ -9,7 +9,9 @@ import ctypes as ct
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsigw.so")
+# SIGW_LIBRARY selects another build of the same library (e.g. the host
+# sanitizer build of build.py --sanitize); there is no fallback either way
+LIB_PATH = os.environ.get("SIGW_LIBRARY") or os.path.join(PKG, "libsigw.so")
 
 SIGW_OK = 0
 SIGW_E_INVALID = -1
@@ -34,7 +36,7 @@ EXPORTS = (
     "sigw_graph_create", "sigw_graph_launch", "sigw_graph_results", "sigw_graph_destroy",
     "sigw_autotune", "sigw_plan_schedule", "sigw_plan_set_schedule", "sigw_spectrum_jackknife",
     "sigw_spectrum_adaptive", "sigw_plan_set_kernel_table", "sigw_spectrum_noalloc",
-    "sigw_kernel_table_w", "sigw_stream_probe",
+    "sigw_kernel_table_w", "sigw_stream_probe", "sigw_shell_modes",
 )
 
 SIGW_TUNE_FORCE = 1
@@ -89,6 +91,7 @@ def lib() -> ct.CDLL:
         "sigw_kernel_table": [ct.POINTER(PlanDesc), ct.c_int32, D, D, D],
         "sigw_kernel_table_w": [ct.POINTER(PlanDesc), ct.c_double, ct.c_int32, D, D, D],
         "sigw_stream_probe": [ct.c_int32, P, ct.c_size_t, ct.c_int32, P, D],
+        "sigw_shell_modes": [ct.c_int32, ct.c_double, ct.c_double, ct.c_double, I32, I32, I64],
         "sigw_white_noise": [P, ct.c_uint64, P],
         "sigw_generate_field": [P, ct.c_int32, ct.c_uint64, ct.POINTER(Lognormal), ct.POINTER(NGMap)],
         "sigw_set_zeta": [P, ct.c_int32, P],

@@ -64,5 +64,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """A copy of the library whose host code (validation, kernel tables,
+    shell logic, footprint, the no-alloc layout) carries AddressSanitizer and
+    UndefinedBehaviorSanitizer checks, for the CPU ABI tests; device code is
+    built as usual.  Lands in _build/sanitize/libsigw.so, never next to the
+    package; load it with SIGW_LIBRARY=<path> and the clang ASan runtime
+    preloaded (the design doc gives the command)."""
+    out_dir = os.path.join(BUILD, "sanitize")
+    os.makedirs(out_dir, exist_ok=True)
+    host_san = ["-g", "-O1", "-fno-omit-frame-pointer",
+                "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj]
+        if src.endswith(".cpp"):
+            cmd[1:1] = ["-x", "hip"]
+            cmd += host_san
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    lib = os.path.join(out_dir, "libsigw.so")
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", lib, "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return lib
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -882,6 +882,44 @@ sigw_status sigw_kernel_table_w(const sigw_plan_desc* d, double w, int32_t m, do
     return SIGW_OK;
 }
 
+sigw_status sigw_shell_modes(int32_t N, double L, double k_lo, double k_hi, int32_t* n2_lo, int32_t* n2_hi,
+                             int64_t* count) {
+    if (!supported_N(N) || !(L > 0.0) || !std::isfinite(L) || !std::isfinite(k_lo) || !std::isfinite(k_hi) ||
+        !(k_hi > k_lo) || !count)
+        return SIGW_E_INVALID;
+    try {
+        sigw_plan P;                       // host state only: the lattice table and the box
+        P.d.N = N;
+        P.d.L = L;
+        P.z.n2max = 3L * (N / 2) * (N / 2);
+        P.lattice_n2 = lattice_n2_table(N);
+        int a = 0, b = -1;
+        *count = 0;
+        if (!shell_modes(&P, k_lo, k_hi, &a, &b)) return SIGW_OK;
+        // modes of the signed index range [-N/2, N/2) with a given square: 1 for
+        // 0 and N/2, 2 for the values in between
+        const int h = N / 2;
+        std::vector<int64_t> one(size_t(h) * h + 1, 0), two(size_t(2) * h * h + 1, 0);
+        for (int m = 0; m <= h; ++m) one[size_t(m) * m] = (m == 0 || m == h) ? 1 : 2;
+        for (int x = 0; x <= h; ++x)
+            for (int y = 0; y <= h; ++y) two[size_t(x * x + y * y)] += one[size_t(x) * x] * one[size_t(y) * y];
+        int64_t c = 0;
+        for (long s2 = 0; s2 <= 2L * h * h; ++s2) {
+            if (!two[size_t(s2)]) continue;
+            for (int z = 0; z <= h; ++z) {
+                const long n2 = s2 + long(z) * z;
+                if (n2 >= a && n2 <= b) c += two[size_t(s2)] * one[size_t(z) * z];
+            }
+        }
+        if (n2_lo) *n2_lo = a;
+        if (n2_hi) *n2_hi = b;
+        *count = c;
+    } catch (const std::bad_alloc&) {
+        return SIGW_E_NOMEM;
+    }
+    return SIGW_OK;
+}
+
 sigw_status sigw_plan_set_kernel_table(sigw_plan_t p, int32_t m, const double* sigma, const double* phi,
                                        const double* edges) {
     if (!p) return SIGW_E_INVALID;

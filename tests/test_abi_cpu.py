@@ -182,3 +182,42 @@ def test_library_constant_w_tables_match_oracle():
     D = ct.POINTER(ct.c_double)
     for bad_w in (0.0, 1.0, -0.2, float("nan")):
         assert L.sigw_kernel_table_w(ct.byref(d), bad_w, 0, None, None, None) == _lib.SIGW_E_INVALID
+
+
+def test_shell_modes_against_oracle_counts():
+    """sigw_shell_modes (the shell logic of every spectrum call) against the
+    oracle's mode counts on the half layout: log bins, thin shells, a shell
+    whose only |n|^2 is 7 (no mode), a negative lower edge, an upper edge far
+    past the lattice, and the Nyquist corner."""
+    import math
+    import workloads as W
+    from oracle import spectrum
+    L = _lib.lib()
+    I32, I64 = ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)
+
+    def lib_count(N, Lb, lo, hi):
+        a, b, c = ct.c_int32(0), ct.c_int32(0), ct.c_int64(-1)
+        assert L.sigw_shell_modes(N, Lb, lo, hi, ct.byref(a), ct.byref(b), ct.byref(c)) == 0
+        return c.value, a.value, b.value
+
+    for N in (16, 32, 64):
+        Lb = 2 * math.pi
+        e, t = W.log_bins(N, Lb, 24)
+        lo, hi = W.shells_from_edges(e)
+        extra_lo = [math.sqrt(7) - 0.01, -5.0, 3.0, math.sqrt(3) * N / 2 - 0.3, 0.0]
+        extra_hi = [math.sqrt(7) + 0.01, 2.0, 1e12, 1e9, 1e-3]
+        lo = np.append(lo, extra_lo)
+        hi = np.append(hi, extra_hi)
+        ref = spectrum.mode_counts(N, Lb, lo, hi)
+        for l_, h_, r in zip(lo, hi, ref):
+            c, a, b = lib_count(N, Lb, float(l_), float(h_))
+            assert c == r, (N, l_, h_, c, r)
+            if c:
+                assert 0 < a <= b <= 3 * (N // 2) ** 2
+    # a box other than 2 pi
+    ref = spectrum.mode_counts(32, 3.0, np.array([2.0]), np.array([9.5]))
+    assert lib_count(32, 3.0, 2.0, 9.5)[0] == ref[0]
+    c = ct.c_int64(0)
+    assert L.sigw_shell_modes(30, 1.0, 0.0, 1.0, None, None, ct.byref(c)) == _lib.SIGW_E_INVALID
+    assert L.sigw_shell_modes(32, 1.0, 2.0, 1.0, None, None, ct.byref(c)) == _lib.SIGW_E_INVALID
+    assert L.sigw_shell_modes(32, 1.0, 0.0, float("inf"), None, None, ct.byref(c)) == _lib.SIGW_E_INVALID
