@@ -8,7 +8,10 @@
 * Graph replays, with eager work of the same plan between them, each equal
   the eager result for the fields the slots hold at that time.
 * Served requests of mixed lattice sizes that overlap on the device give
-  the same bits as each request run alone.
+  the same bits as each request run alone: small lattices (16^3, 32^3), and
+  the served stream's own mix (64^3, 128^3, 256^3 with all terms per pass,
+  384^3 with 25 terms per pass and the smaller-grid and pruning paths its
+  targets take).
 """
 import math
 
@@ -141,3 +144,26 @@ def test_served_requests_equal_standalone():
         om, nb = _alone(job, alpha_chunk=backend.chunk_for(job.N))
         np.testing.assert_array_equal(d.omega, om)
         np.testing.assert_array_equal(d.nmodes, nb)
+
+
+def test_served_stream_mix_equals_standalone():
+    from paper_2605_27231_amd.serve import GpuBackend, SpectrumServer
+    stream = W.request_stream(400, 50.0)
+    picks = []
+    for N, n in ((64, 3), (128, 3), (256, 2), (384, 1)):
+        picks += [r for r in stream if r.job.N == N][:n]
+    reqs = [W.Request(rid=i, arrival=0.001 * i, job=r.job) for i, r in enumerate(picks)]
+    backend = GpuBackend("f32")
+    srv = SpectrumServer(backend, int(150e9), prewarm={64: 2, 128: 2, 256: 2, 384: 1})
+    print(f"serving {len(reqs)} requests of the C5 mix", flush=True)
+    done = srv.serve(reqs)
+    srv.close()
+    assert sorted(d.rid for d in done) == list(range(len(reqs)))
+    assert srv.peak_inflight >= 3
+    for d in done:
+        job = reqs[d.rid].job
+        print(f"  request {d.rid} N={job.N} alone", flush=True)
+        om, nb = _alone(job, alpha_chunk=backend.chunk_for(job.N), autotune=1)
+        np.testing.assert_array_equal(d.omega, om)
+        np.testing.assert_array_equal(d.nmodes, nb)
+        assert (nb > 0).all()
