@@ -47,9 +47,12 @@ HBM_PEAK_GBS = 8000.0
 # configuration and launch mix), averaged over the launches of one spectrum,
 # from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes on `bench.py --quick`,
 # scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
-# source they were taken on (see the summaries in profiles/).
+# source they were taken on and only for the workload whose launch mix they
+# cover (see the summaries in profiles/).
 COUNTER_SOURCE_SHA = "2b50ff3aa49d9722"
-COUNTER_TRAFFIC = {"xprod": 30949007162.5, "ypass": 48859741577.8, "gen_z": 18802134179.3}
+COUNTER_TRAFFIC = {
+    "local256": {"xprod": 31409546610.0, "ypass": 49640259951.4, "gen_z": 19114016844.6},
+}
 
 
 def kernel_source_sha() -> str:
@@ -346,8 +349,8 @@ def run_gpu(args):
         "value": value, "dt": dt, "n_targets": n_targets, "omega_seed_last": om.tolist(),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": (COUNTER_TRAFFIC.get(dom) if kernel_source_sha() == COUNTER_SOURCE_SHA
-                                 else None),
+                     "traffic": (COUNTER_TRAFFIC.get(args.workload, {}).get(dom)
+                                 if kernel_source_sha() == COUNTER_SOURCE_SHA else None),
                      "kernel": dom,
                      "alg_bytes_per_launch": ab[dom], "avg_launch_ms": round(ms_d, 4),
                      "launches": n_d, "end_to_end": e2e},
