@@ -52,6 +52,7 @@ HBM_PEAK_GBS = 8000.0
 COUNTER_SOURCE_SHA = "2b50ff3aa49d9722"
 COUNTER_TRAFFIC = {
     "local256": {"xprod": 31409546610.0, "ypass": 49640259951.4, "gen_z": 19114016844.6},
+    "exptail512": {"xprod": 54185035922.2, "ypass": 29380181337.5, "gen_z": 11882033747.4},
 }
 
 
