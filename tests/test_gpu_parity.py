@@ -94,7 +94,8 @@ def test_generate_field(prec, ngmap, L):
 # ------------------------------------------------------- source convolutions
 @pytest.mark.parametrize("N,k_b,prec,n_alpha", [
     (16, 3.0, "f64", 50), (32, 5.5, "f64", 50), (64, 9.0, "f64", 50), (32, 5.5, "f32", 50),
-    (128, 20.0, "f32", 6), (384, 50.0, "f32", 2), (512, 60.0, "f32", 2), (256, 30.0, "f64", 2)])
+    (128, 20.0, "f32", 6), (256, 30.0, "f32", 6), (384, 50.0, "f32", 2), (384, 50.0, "f64", 2),
+    (512, 60.0, "f32", 2), (256, 30.0, "f64", 2)])
 def test_source_convolutions(tabs, N, k_b, prec, n_alpha):
     _say(f"qhat N={N} k={k_b} prec={prec} n_alpha={n_alpha}")
     L = 2 * math.pi
