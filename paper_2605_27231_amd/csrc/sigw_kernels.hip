@@ -53,6 +53,16 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + s;
 }
 
+// Workgroup barrier for LDS hand-offs only: it waits for this wavefront's
+// LDS operations (lgkmcnt) and nothing else.  __syncthreads makes every LDS
+// write visible to the workgroup, and since global-to-LDS loads write LDS,
+// it also waits for all of those in flight (vmcnt): a tile requested for
+// the next term would have to land at the very next barrier.  With this
+// barrier it stays in flight.  The memory clobber keeps the compiler from
+// moving memory accesses across it; a caller that needs a global-to-LDS
+// load to have landed waits for it explicitly.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Layout of the gradient fields U (written by ypass3, read by xprod): tiles
 // of TZT z values, 128 bytes.  Element (kx, y, z) of a field sits at
 //   ((y * (N / TZT) + z / TZT) * hs + kx) * TZT + z % TZT,
@@ -1037,16 +1047,18 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
         __syncthreads();                  // ... and every wavefront's; Z is free again
         rawc = raw;
         phase1();
-        __syncthreads();
-        // phase 1 is done with the tile: request the next one.  Phase 1
-        // makes no vector memory access (its twiddles come from LDS), since
-        // such an access would complete only after every tile load in flight.
+        lds_barrier();
+        // phase 1 is done with the tile: request the next one; it stays in
+        // flight through phase 2 and the products (the barriers until the
+        // next term's first one hand off LDS only).  Phase 1 makes no vector
+        // memory access (its twiddles come from LDS), since such an access
+        // would complete only after every tile load in flight.
         if (a + 1 < a0 + na) issue_tile(a + 1, raw);
         TPRegs<C, N, +1, NLI, NT, true> g;
         g.run(Z, tid);
-        __syncthreads();
+        lds_barrier();
         g.store([&](int line, int x, C v) { Z[line * LS + x] = v; }, tid);
-        __syncthreads();
+        lds_barrier();
         const R s = sigma[a] * dV;
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
