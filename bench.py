@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a 1 GiB copy (reads x2.0, writes x1.0); valid only for the kernel
 # source they were taken on and only for the workload whose launch mix they
 # cover (see the summaries in profiles/).
-COUNTER_SOURCE_SHA = "2b50ff3aa49d9722"
+COUNTER_SOURCE_SHA = "defb99cec9076375"
 COUNTER_TRAFFIC = {
-    "local256": {"xprod": 31409546610.0, "ypass": 49640259951.4, "gen_z": 19114016844.6},
-    "exptail512": {"xprod": 54185035922.2, "ypass": 29380181337.5, "gen_z": 11882033747.4},
+    "local256": {"xprod": 31462149364.1, "ypass": 49640423669.9, "gen_z": 19115834710.4},
+    "exptail512": {"xprod": 54935838040.2, "ypass": 29380982619.7, "gen_z": 11891645119.8},
 }
 
 

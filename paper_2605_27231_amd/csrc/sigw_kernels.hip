@@ -1041,24 +1041,33 @@ __global__ __launch_bounds__(256, OCC) void k_xprod(const typename CplxOf<R>::T*
         }
     };
 
+    // Barriers inside a term.  From 384^3 on they hand off LDS only, so the
+    // next tile stays in flight through phase 2 and the products (512^3:
+    // 15.2-15.5 vs 16.4 ms per launch, 1.6% more HBM reads); up to 256^3 the
+    // plain barrier, which lets that tile land by the end of phase 2: the
+    // LDS-only form read 6% more from HBM there (the two halves of a tile
+    // line, fetched by neighbouring blocks, shared L2 less often) for no
+    // gain per launch.
+    auto mid_barrier = [] {
+        if constexpr (N >= 384) lds_barrier();
+        else __syncthreads();
+    };
     issue_tile(a0, raw);
     for (int a = a0; a < a0 + na; ++a) {
         __builtin_amdgcn_s_waitcnt(0);    // this wavefront's loads of tile a have landed
         __syncthreads();                  // ... and every wavefront's; Z is free again
         rawc = raw;
         phase1();
-        lds_barrier();
-        // phase 1 is done with the tile: request the next one; it stays in
-        // flight through phase 2 and the products (the barriers until the
-        // next term's first one hand off LDS only).  Phase 1 makes no vector
-        // memory access (its twiddles come from LDS), since such an access
-        // would complete only after every tile load in flight.
+        mid_barrier();
+        // phase 1 is done with the tile: request the next one.  Phase 1
+        // makes no vector memory access (its twiddles come from LDS), since
+        // such an access would complete only after every tile load in flight.
         if (a + 1 < a0 + na) issue_tile(a + 1, raw);
         TPRegs<C, N, +1, NLI, NT, true> g;
         g.run(Z, tid);
-        lds_barrier();
+        mid_barrier();
         g.store([&](int line, int x, C v) { Z[line * LS + x] = v; }, tid);
-        lds_barrier();
+        mid_barrier();
         const R s = sigma[a] * dV;
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
