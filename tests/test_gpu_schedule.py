@@ -88,6 +88,29 @@ def test_schedules_bit_identical_256():
         np.testing.assert_array_equal(om.view(np.uint64), res[0][0].view(np.uint64))
 
 
+def test_schedules_bit_identical_384_and_repeatable():
+    """At 384^3 the x pass hands off LDS between its phases with barriers
+    that leave the next tile's loads in flight: every schedule must still
+    give the same bits, and the same schedule the same bits twice."""
+    job = W.config_local_ng(256, 64)
+    L = job.L
+    targets = np.array([15.0, 23.0, 40.0])
+    lo, hi = targets - 0.5, targets + 0.5
+    sub = W.Job(N=384, L=L, spectrum=job.spectrum, ngmap=job.ngmap, k_lo=lo, k_hi=hi, targets=targets)
+    _say("schedules 384^3 f32, 3 targets")
+    with P.Plan(384, L=L, prec="f32") as pl:
+        pl.generate_field(0, 2, job.spectrum, job.ngmap)
+        res, count = _all_schedules(pl, 0, sub)
+        pl.set_schedule(0)
+        again = pl.spectrum(0, sub.targets, sub.k_lo, sub.k_hi)
+    assert count >= 2
+    np.testing.assert_array_equal(again[0].view(np.uint64), res[0][0].view(np.uint64))
+    for om, nb in res[1:]:
+        np.testing.assert_array_equal(nb, res[0][1])
+        np.testing.assert_array_equal(om.view(np.uint64), res[0][0].view(np.uint64))
+    assert np.all(res[0][1] > 0)
+
+
 def test_autotune_choice_and_reuse():
     job = _job64()
     _say("autotune 128^3 f32")
